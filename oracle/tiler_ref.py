@@ -1,0 +1,207 @@
+"""A reading of the paper's SGEMM_NN tile algorithm (test infrastructure).
+
+Section V-A (Algorithm 2) tiles C into blocks whose sizes are kernels of the
+install-time kernel array (Table 1), then derives the A and B blocks from
+them.  Section V-A's "Minimal Memops" principle counts the data moved from
+cache to registers by a tiling with blocks m_i x n_i as
+
+    (sum_i (m_i + n_i)) * K + 2*M*N,
+
+so the tiling is judged by S = sum_i (m_i + n_i).  The paper's worked example
+(Fig. 2, 15 x 15 SGEMM_NN) costs 72K + 450 with its method.
+
+Readings taken where the algorithm is silent or ambiguous:
+  * TileSingleDim(L, sizes): greedy, largest size first; if the last piece r
+    is smaller than half the largest size d and at least one d was used, one
+    d and the r are replaced by ceil((d+r)/2) and floor((d+r)/2) ("average").
+  * N <= 13 branch: a remainder strip that is not itself a kernel height for
+    n_c = N is tiled again by the same rule.
+  * M == 8 with N > 13 falls into the "M < 12" branch; the empty (M-8)-row
+    strip is dropped.
+  * "M mod 4 == 1" case: the 3-row strip uses the 3-row kernels' n-range.
+  * ExtendTo8 / ExtendTo16: the run of 4-row strips is merged greedily into
+    heights {8, 4} and {16, 12, 8, 4} respectively.
+  * CompareLessMemops: smaller S wins; on a tie fewer blocks, then the
+    16-based merge.
+Only the 15 x 15 case is fixed by a number the paper prints; the other
+branches are checked by invariants (exact cover, kernel membership).
+"""
+from __future__ import annotations
+
+from typing import Dict, List, Sequence, Tuple
+
+# Table 1: the generated kernel array.  For each (type, layout): a list of
+# (m_c, n_c-values).  TT entries are the NN ones mirrored (n_c x m_c).
+def _rng(a, b):
+    return list(range(a, b + 1))
+
+
+TABLE1: Dict[str, Dict[str, List[Tuple[int, List[int]]]]] = {
+    "S": {
+        "NN": [(16, _rng(1, 4)), (12, _rng(1, 6)), (8, _rng(1, 8)), (4, _rng(1, 13)),
+               (3, _rng(1, 13)), (2, _rng(1, 13)), (1, _rng(1, 13))],
+        "NT": [(16, _rng(1, 4)), (12, _rng(1, 8)), (8, _rng(1, 8)), (4, _rng(1, 20)),
+               (3, _rng(1, 24)), (2, _rng(1, 28)), (1, _rng(1, 32))],
+        "TN": [(4, _rng(1, 4)), (3, _rng(1, 5)), (2, _rng(1, 7)), (1, _rng(1, 10))],
+    },
+    "D": {
+        "NN": [(8, _rng(1, 4)), (4, _rng(1, 8)), (3, _rng(1, 8)), (2, _rng(1, 15)), (1, _rng(1, 15))],
+        "NT": [(8, _rng(1, 4)), (4, _rng(1, 8)), (3, _rng(1, 8)), (2, _rng(1, 20)), (1, _rng(1, 20))],
+        "TN": [(4, _rng(1, 4)), (3, _rng(1, 5)), (2, _rng(1, 7)), (1, _rng(1, 10))],
+    },
+    "C": {
+        "NN": [(8, _rng(1, 4)), (4, _rng(1, 9)), (3, _rng(1, 9)), (2, _rng(1, 12)), (1, _rng(1, 20))],
+        "NT": [(8, _rng(1, 4)), (4, _rng(1, 8)), (3, _rng(1, 8)), (2, _rng(1, 12)), (1, _rng(1, 20))],
+        "TN": [(4, _rng(1, 9)), (3, _rng(1, 9)), (2, _rng(1, 12)), (1, _rng(1, 20))],
+    },
+    "Z": {
+        "NN": [(4, _rng(1, 4)), (3, _rng(1, 4)), (2, _rng(1, 7)), (1, _rng(1, 10))],
+        "NT": [(4, _rng(1, 4)), (3, _rng(1, 4)), (2, _rng(1, 7)), (1, _rng(1, 10))],
+        "TN": [(4, _rng(1, 4)), (3, _rng(1, 4)), (2, _rng(1, 7)), (1, _rng(1, 10))],
+    },
+}
+
+
+def kernel_set(typ: str, layout: str) -> set:
+    """All (m_c, n_c) kernels of Table 1 for a type and layout."""
+    if layout == "TT":
+        return {(n, m) for (m, n) in kernel_set(typ, "NN")}
+    return {(m, n) for (m, ns) in TABLE1[typ][layout] for n in ns}
+
+
+def kernel_count(typ: str) -> int:
+    return sum(len(kernel_set(typ, lay)) for lay in ("NN", "NT", "TN", "TT"))
+
+
+# The SGEMM_NN n-range per strip height.
+NN_NMAX = {h: max(ns) for (h, ns) in TABLE1["S"]["NN"]}
+
+
+def tile_single_dim(L: int, sizes: Sequence[int]) -> List[Tuple[int, int]]:
+    """TileSingleDim: split L into pieces from ``sizes``; returns (dim, nums)
+    runs.  Greedy biggest-first; a too-small last piece is averaged with the
+    previous one (reading described in the module docstring)."""
+    if L <= 0:
+        return []
+    d = max(sizes)
+    n1, r = divmod(L, d)
+    if r == 0:
+        return [(d, n1)]
+    if n1 == 0:
+        return [(r, 1)] if r in sizes else tile_single_dim(r, [s for s in sizes if s <= r])
+    if 2 * r < d:
+        a, b = (d + r + 1) // 2, (d + r) // 2
+        runs = [(d, n1 - 1)] if n1 > 1 else []
+        runs += [(a, 1), (b, 1)] if a != b else [(a, 2)]
+        return runs
+    return [(d, n1), (r, 1)]
+
+
+def _expand(runs):
+    out = []
+    for dim, nums in runs:
+        out += [dim] * nums
+    return out
+
+
+def _strip_blocks(heights: List[int], n_tilings: List[List[Tuple[int, int]]]):
+    """Combine: row strips (in order) x each strip's column tiling -> blocks
+    (i0, j0, m_c, n_c)."""
+    blocks = []
+    i0 = 0
+    for h, nt in zip(heights, n_tilings):
+        j0 = 0
+        for w in _expand(nt):
+            blocks.append((i0, j0, h, w))
+            j0 += w
+        i0 += h
+    return blocks
+
+
+def _tile_n_for(h: int, N: int):
+    return tile_single_dim(N, list(range(1, NN_NMAX[h] + 1)))
+
+
+def _n_le_13_heights(M: int, N: int) -> List[int]:
+    heights = []
+    rem = M
+    while rem > 0:
+        cands = [h for h in NN_NMAX if NN_NMAX[h] >= N and h <= rem]
+        h = max(cands)
+        times = rem // h
+        heights += [h] * times
+        rem -= h * times
+    return heights
+
+
+def _merge(count4: int, parts: Sequence[int]) -> List[int]:
+    """Merge ``count4`` consecutive 4-row strips greedily into heights from
+    ``parts`` (all multiples of 4)."""
+    rows = 4 * count4
+    out = []
+    for p in sorted(parts, reverse=True):
+        while rows >= p:
+            out.append(p)
+            rows -= p
+    assert rows == 0
+    return out
+
+
+def memops_S(blocks) -> int:
+    """sum_i (m_i + n_i) over the blocks of C (the K coefficient)."""
+    return sum(m + n for (_, _, m, n) in blocks)
+
+
+def memops(blocks, M: int, N: int, K: int) -> int:
+    """Loads from cache to registers: (sum (m_i + n_i)) K + 2 M N."""
+    return memops_S(blocks) * K + 2 * M * N
+
+
+def sgemm_nn_tile(M: int, N: int):
+    """Algorithm 2 (SGEMM_NN) -> list of C blocks (i0, j0, m_c, n_c).
+
+    A blocks are rows [i0, i0+m_c) x all K and B blocks are all K x columns
+    [j0, j0+n_c): the tiling never splits K."""
+    if M <= 0 or N <= 0:
+        return []
+    if N <= 13:
+        heights = _n_le_13_heights(M, N)
+        return _strip_blocks(heights, [[(N, 1)]] * len(heights))
+    if M < 8:
+        heights = _expand(tile_single_dim(M, [1, 2, 3, 4]))
+        return _strip_blocks(heights, [_tile_n_for(h, N) for h in heights])
+    if M == 9:
+        heights = [4, 3, 2]
+        return _strip_blocks(heights, [_tile_n_for(h, N) for h in heights])
+    if M < 12:
+        heights = [8] + ([M - 8] if M > 8 else [])
+        return _strip_blocks(heights, [_tile_n_for(h, N) for h in heights])
+    if M == 12:
+        return _strip_blocks([12], [_tile_n_for(12, N)])
+    q, r = divmod(M, 4)
+    tail = [r] if r else []
+    if r == 1:
+        q -= 1
+        tail = [3, 2]
+    cands = []
+    for tag, parts in (("8", (8, 4)), ("16", (16, 12, 8, 4))):
+        heights = _merge(q, parts) + tail
+        blocks = _strip_blocks(heights, [_tile_n_for(h, N) for h in heights])
+        cands.append((memops_S(blocks), len(blocks), 0 if tag == "16" else 1, blocks))
+    cands.sort(key=lambda c: c[:3])
+    return cands[0][3]
+
+
+def strip_dp_optimum(M: int, N: int, nmax: Dict[int, int] = None) -> int:
+    """Smallest S over all tilings made of full-width row strips, each strip
+    of height h cut into ceil(N / nmax[h]) pieces: best[m] = min_h best[m-h]
+    + ceil(N/nmax[h]) * h + N.  A lower bound for Algorithm 2's S."""
+    nmax = NN_NMAX if nmax is None else nmax
+    INF = float("inf")
+    best = [0] + [INF] * M
+    for m in range(1, M + 1):
+        for h, nm in nmax.items():
+            if h <= m and best[m - h] < INF:
+                pieces = -(-N // nm)
+                best[m] = min(best[m], best[m - h] + pieces * h + N)
+    return int(best[M])

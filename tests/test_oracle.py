@@ -1,0 +1,192 @@
+"""Pins for the FP64 GEMM oracle (CPU only).
+
+Each check compares the oracle with something other than itself: exact
+closed forms (identity, permutation, rank-one), special cases, brute force
+over tiny integer matrices against the outer-product expansion, numpy's
+float64 matmul (a library routine), and layout metamorphic relations.  A
+dropped term, a wrong sign, a swapped index or a transposed operand in the
+oracle fails at least one of them.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2208_09822_amd import inputs
+
+LAY = {"NN": (0, 0), "TN": (1, 0), "NT": (0, 1), "TT": (1, 1)}
+
+
+def col_major(mat):
+    """2-D array -> flat column-major FP32 storage, ld = rows."""
+    return np.asarray(mat, dtype=np.float32).T.reshape(-1).copy()
+
+
+def stored(opmat, trans):
+    """The stored matrix whose op() is ``opmat``."""
+    return opmat.T if trans else opmat
+
+
+def run(layout, opA, opB, alpha, beta, C0):
+    ta, tb = LAY[layout]
+    M, K = opA.shape
+    _, N = opB.shape
+    As = stored(opA, ta); Bs = stored(opB, tb)
+    return oracle.gemm(ta, tb, M, N, K, alpha, col_major(As), max(As.shape[0], 1),
+                       col_major(Bs), max(Bs.shape[0], 1), beta,
+                       None if C0 is None else col_major(C0), max(M, 1))
+
+
+@pytest.mark.parametrize("layout", list(LAY))
+def test_identity(layout):
+    rng = np.random.default_rng(1)
+    M, N = 7, 5
+    B = rng.integers(-4, 5, (M, N)).astype(np.float32)
+    C0 = rng.integers(-4, 5, (M, N)).astype(np.float32)
+    out = run(layout, np.eye(M, dtype=np.float32), B, 1.5, -0.5, C0)
+    assert np.array_equal(out, 1.5 * B.astype(np.float64) - 0.5 * C0)
+
+
+@pytest.mark.parametrize("layout", list(LAY))
+def test_permutation_rows_and_cols(layout):
+    rng = np.random.default_rng(2)
+    M, K, N = 6, 6, 9
+    perm = rng.permutation(M)
+    P = np.zeros((M, K), np.float32)
+    P[np.arange(M), perm] = 1.0
+    B = rng.uniform(-1, 1, (K, N)).astype(np.float32)
+    out = run(layout, P, B, 1.0, 0.0, None)
+    assert np.array_equal(out, B[perm].astype(np.float64))
+    # permutation on the right permutes columns
+    A = rng.uniform(-1, 1, (M, N)).astype(np.float32)
+    Q = np.zeros((N, N), np.float32)
+    qp = rng.permutation(N)
+    Q[qp, np.arange(N)] = 1.0  # column j of A@Q is column qp[j] of A
+    out2 = run(layout, A, Q, 1.0, 0.0, None)
+    assert np.array_equal(out2, A[:, qp].astype(np.float64))
+
+
+@pytest.mark.parametrize("layout", list(LAY))
+def test_rank_one_closed_form(layout):
+    rng = np.random.default_rng(3)
+    M, N, K = 9, 4, 13
+    x = rng.integers(-4, 5, M).astype(np.float32)
+    y = rng.integers(-4, 5, N).astype(np.float32)
+    opA = np.repeat(x[:, None], K, axis=1)       # x 1^T
+    opB = np.repeat(y[None, :], K, axis=0)       # 1 y^T
+    C0 = rng.integers(-4, 5, (M, N)).astype(np.float32)
+    out = run(layout, opA, opB, -2.0, 1.5, C0)
+    expect = -2.0 * K * np.outer(x, y).astype(np.float64) + 1.5 * C0
+    assert np.array_equal(out, expect)
+
+
+def test_alpha_zero_and_k_zero_do_not_read_ab():
+    C0 = np.arange(12, dtype=np.float32).reshape(3, 4)
+    # A and B passed as None: the oracle must not touch them
+    for alpha, k in ((0.0, 5), (1.0, 0)):
+        out = oracle.gemm(0, 0, 3, 4, k, alpha, None, 3, None, max(k, 1), 0.5, col_major(C0), 3)
+        assert np.array_equal(out, 0.5 * C0.astype(np.float64))
+
+
+def test_beta_zero_ignores_nan_c():
+    rng = np.random.default_rng(4)
+    A = rng.uniform(-1, 1, (4, 3)).astype(np.float32)
+    B = rng.uniform(-1, 1, (3, 5)).astype(np.float32)
+    C0 = np.full((4, 5), np.nan, np.float32)
+    out = run("NN", A, B, 1.0, 0.0, C0)
+    assert np.all(np.isfinite(out))
+    out_b = run("NN", A, B, 1.0, 1.0, C0)
+    assert np.all(np.isnan(out_b))
+
+
+def test_nan_in_a_propagates_to_its_row_only():
+    A = np.ones((3, 2), np.float32); A[1, 0] = np.nan
+    B = np.ones((2, 4), np.float32)
+    out = run("NN", A, B, 1.0, 0.0, None)
+    assert np.all(np.isnan(out[1])) and np.all(np.isfinite(out[[0, 2]]))
+
+
+def test_empty_shapes():
+    assert oracle.gemm(0, 0, 0, 5, 3, 1.0, None, 1, None, 3, 1.0, None, 1).shape == (0, 5)
+    assert oracle.gemm(0, 0, 4, 0, 3, 1.0, None, 4, None, 3, 1.0, None, 4).shape == (4, 0)
+
+
+def test_brute_force_tiny_integer():
+    """Every op(A), op(B) over {-1,0,1} for M, N, K <= 2 (all four layouts),
+    against the outer-product expansion C = sum_p a_p b_p^T (numpy.outer)."""
+    vals = (-1.0, 0.0, 1.0)
+    for M, N, K in itertools.product((1, 2), repeat=3):
+        mats_a = [np.array(v, np.float32).reshape(M, K) for v in itertools.product(vals, repeat=M * K)]
+        mats_b = [np.array(v, np.float32).reshape(K, N) for v in itertools.product(vals, repeat=K * N)]
+        if M * K * K * N > 8:  # keep 2x2x2 at a strided sample of pairs
+            pairs = [(a, b) for ia, a in enumerate(mats_a) for ib, b in enumerate(mats_b)
+                     if (ia * 7 + ib) % 5 == 0]
+        else:
+            pairs = [(a, b) for a in mats_a for b in mats_b]
+        for layout in LAY:
+            for a, b in pairs:
+                expect = sum(np.outer(a[:, p], b[p, :]) for p in range(K))
+                out = run(layout, a, b, 1.0, 0.0, None)
+                assert np.array_equal(out, expect), (layout, a, b)
+
+
+@pytest.mark.parametrize("layout", list(LAY))
+def test_against_numpy_matmul(layout):
+    rng = np.random.default_rng(5)
+    for M, N, K in ((1, 1, 1), (5, 3, 80), (17, 33, 31), (80, 80, 80), (64, 1, 48)):
+        opA = rng.uniform(-1, 1, (M, K)).astype(np.float32)
+        opB = rng.uniform(-1, 1, (K, N)).astype(np.float32)
+        C0 = rng.uniform(-1, 1, (M, N)).astype(np.float32)
+        out = run(layout, opA, opB, 0.75, -1.25, C0)
+        ref = 0.75 * (opA.astype(np.float64) @ opB.astype(np.float64)) - 1.25 * C0.astype(np.float64)
+        bound = (K + 2) * 2.0 ** -53 * (0.75 * (np.abs(opA) @ np.abs(opB)) + 1.25 * np.abs(C0))
+        assert np.all(np.abs(out - ref) <= 2 * bound + 1e-300)
+        # integer inputs: exact
+        ia = rng.integers(-4, 5, (M, K)).astype(np.float32)
+        ib = rng.integers(-4, 5, (K, N)).astype(np.float32)
+        assert np.array_equal(run(layout, ia, ib, 1.0, 0.0, None),
+                              ia.astype(np.float64) @ ib.astype(np.float64))
+
+
+def test_layout_metamorphic():
+    """Same op(A), op(B) in every stored layout gives the same C; and
+    op = TT equals (NN with the operands swapped) transposed."""
+    rng = np.random.default_rng(6)
+    M, N, K = 11, 7, 9
+    opA = rng.uniform(-1, 1, (M, K)).astype(np.float32)
+    opB = rng.uniform(-1, 1, (K, N)).astype(np.float32)
+    outs = [run(l, opA, opB, 1.0, 0.0, None) for l in LAY]
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+    # TT with stored A (K x M) = opA^T, stored B (N x K) = opB^T:
+    # C = A_s^T B_s^T = (B_s A_s)^T  -> NN of (B_s, A_s), transposed
+    As = opA.T.copy(); Bs = opB.T.copy()
+    tt = oracle.gemm(1, 1, M, N, K, 1.0, col_major(As), K, col_major(Bs), N, 0.0, None, M)
+    nn = oracle.gemm(0, 0, N, M, K, 1.0, col_major(Bs), N, col_major(As), K, 0.0, None, N)
+    assert np.array_equal(tt, nn.T)
+
+
+def test_leading_dimension_padding_ignored():
+    rng = np.random.default_rng(7)
+    M, N, K = 5, 6, 7
+    A = rng.uniform(-1, 1, (M, K)).astype(np.float32)
+    B = rng.uniform(-1, 1, (K, N)).astype(np.float32)
+    base = oracle.gemm(0, 0, M, N, K, 1.0, col_major(A), M, col_major(B), K, 0.0, None, M)
+    Ap = np.full((M + 3, K), 1e30, np.float32); Ap[:M] = A
+    Bp = np.full((K + 2, N), -1e30, np.float32); Bp[:K] = B
+    padded = oracle.gemm(0, 0, M, N, K, 1.0, col_major(Ap), M + 3, col_major(Bp), K + 2, 0.0, None, M)
+    assert np.array_equal(base, padded)
+
+
+def test_batch_driver_matches_single_calls():
+    ps = inputs.uneven_batch(300, seed=11)
+    out, secs, off = oracle.gemm_batch(ps, nthreads=4)
+    assert secs >= 0
+    for q in range(0, ps.count, 37):
+        M, N = int(ps.m[q]), int(ps.n[q])
+        single = oracle.gemm(int(ps.trans[q]) & 1, int(ps.trans[q]) >> 1, M, N, int(ps.k[q]),
+                             float(ps.alpha[q]), ps.A(q), int(ps.lda[q]), ps.B(q), int(ps.ldb[q]),
+                             float(ps.beta[q]), ps.C(q), int(ps.ldc[q]))
+        got = out[off[q]:off[q] + M * N].reshape(N, M).T
+        assert np.array_equal(single, got)
