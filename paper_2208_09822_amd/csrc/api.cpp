@@ -1,0 +1,315 @@
+// C ABI of libiaat (include/iaat.h): context, one-problem calls, batched
+// calls, and plan introspection.  Host work per call is O(1); per-problem
+// validation and plan lookup of the batched forms run on the device.
+#include <hip/hip_runtime.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <atomic>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "iaat_internal.h"
+#include "kernels.h"
+#include "tiler.h"
+
+using namespace iaat;
+
+struct iaat_ctx {
+  int device = 0;
+  int num_cu = 0;
+  int vb_grid = 0;
+  std::vector<PlanEntry> table;
+  PlanEntry* table_dev = nullptr;
+  uint32_t* ctr_dev = nullptr;
+  std::atomic<uint64_t> slot_next{0};
+  // staging for descriptors handed over in host memory
+  std::mutex stage_mu;
+  iaat_problem* stage_host = nullptr;
+  iaat_problem* stage_dev = nullptr;
+  int64_t stage_cap = 0;
+  hipEvent_t stage_evt = nullptr;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(IAAT_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+const char* arg_name(int st) {
+  switch (st) {
+    case -2: return "ta";
+    case -3: return "tb/trans";
+    case -4: return "m";
+    case -5: return "n";
+    case -6: return "k";
+    case -8: return "A";
+    case -9: return "lda";
+    case -10: return "B";
+    case -11: return "ldb";
+    case -13: return "C";
+    case -14: return "ldc";
+    default: return "?";
+  }
+}
+
+std::once_flag g_default_checked;
+std::string g_default_error;
+
+void free_ctx(iaat_ctx* c) {
+  if (!c) return;
+  DeviceGuard g(c->device);
+  if (c->table_dev) (void)hipFree(c->table_dev);
+  if (c->ctr_dev) (void)hipFree(c->ctr_dev);
+  if (c->stage_dev) (void)hipFree(c->stage_dev);
+  if (c->stage_host) (void)hipHostFree(c->stage_host);
+  if (c->stage_evt) (void)hipEventDestroy(c->stage_evt);
+  delete c;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* iaat_last_error(void) { return g_err.c_str(); }
+
+int iaat_create(iaat_ctx_t* out, int device, const char* tile_table_path) {
+  g_err.clear();
+  if (!out) return fail(-1, "iaat_create: out is NULL");
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+    return fail(-2, "iaat_create: no HIP device %d (%d visible)", device, ndev);
+  DeviceGuard g(device);
+  iaat_ctx* c = new iaat_ctx;
+  c->device = device;
+  std::string why;
+  const char* path = tile_table_path;
+  if (!path || !*path) path = getenv("IAAT_TILE_TABLE");
+  if (path && *path) {
+    if (load_table(path, c->table, &why) != 0) {
+      delete c;
+      return fail(IAAT_ERR_TABLE, "iaat_create: %s", why.c_str());
+    }
+  } else {
+    build_default_table(c->table);
+    std::call_once(g_default_checked, [&] {
+      for (int lay = 0; lay < kLayouts && g_default_error.empty(); ++lay)
+        for (int m = 1; m <= kSuper && g_default_error.empty(); ++m)
+          for (int n = 1; n <= kSuper; ++n)
+            if (!check_plan(m, n, c->table[plan_index(lay, m, n)], &g_default_error)) break;
+    });
+    if (!g_default_error.empty()) {
+      delete c;
+      return fail(IAAT_ERR_TABLE, "iaat_create: built-in table: %s", g_default_error.c_str());
+    }
+  }
+  hipError_t e;
+  if ((e = hipDeviceGetAttribute(&c->num_cu, hipDeviceAttributeMultiprocessorCount, device)) !=
+      hipSuccess) {
+    free_ctx(c);
+    return hip_fail(e, "iaat_create: device attribute");
+  }
+  int per_cu = 0;
+  if ((e = vbatched_occupancy(&per_cu)) != hipSuccess || per_cu < 1) {
+    free_ctx(c);
+    return hip_fail(e, "iaat_create: occupancy");
+  }
+  c->vb_grid = per_cu * c->num_cu;
+  const size_t tbytes = sizeof(PlanEntry) * c->table.size();
+  const size_t cbytes = sizeof(uint32_t) * kCtrPerCall * kCtrSlots;
+  if (hipMalloc(&c->table_dev, tbytes) != hipSuccess || hipMalloc(&c->ctr_dev, cbytes) != hipSuccess) {
+    free_ctx(c);
+    return fail(IAAT_ERR_NOMEM, "iaat_create: device allocation failed");
+  }
+  if ((e = hipMemcpy(c->table_dev, c->table.data(), tbytes, hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemset(c->ctr_dev, 0, cbytes)) != hipSuccess ||
+      (e = hipEventCreateWithFlags(&c->stage_evt, hipEventDisableTiming)) != hipSuccess ||
+      (e = hipDeviceSynchronize()) != hipSuccess) {
+    free_ctx(c);
+    return hip_fail(e, "iaat_create: setup");
+  }
+  *out = c;
+  return IAAT_OK;
+}
+
+int iaat_destroy(iaat_ctx_t ctx) {
+  free_ctx(ctx);
+  return IAAT_OK;
+}
+
+int iaat_gemm(iaat_ctx_t ctx, int ta, int tb, int64_t m, int64_t n, int64_t k, float alpha,
+              const float* A, int64_t lda, const float* B, int64_t ldb, float beta, float* C,
+              int64_t ldc, iaat_stream_t stream) {
+  if (!ctx) return fail(-1, "iaat_gemm: ctx is NULL");
+  if (ta != IAAT_OP_N && ta != IAAT_OP_T) return fail(-2, "iaat_gemm: ta=%d", ta);
+  if (tb != IAAT_OP_N && tb != IAAT_OP_T) return fail(-3, "iaat_gemm: tb=%d", tb);
+  const int layout = ta | (tb << 1);
+  const int st = validate(layout, m, n, k, lda, ldb, ldc, alpha, A, B, C);
+  if (st != 0)
+    return fail(st, "iaat_gemm: invalid %s (m=%lld n=%lld k=%lld lda=%lld ldb=%lld ldc=%lld)",
+                arg_name(st), (long long)m, (long long)n, (long long)k, (long long)lda,
+                (long long)ldb, (long long)ldc);
+  if (m == 0 || n == 0) return IAAT_OK;
+  DeviceGuard g(ctx->device);
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e;
+  if (alpha == 0.0f || k == 0) {
+    e = launch_scale_f32(C, (int)m, (int)n, (int)ldc, beta, s);
+    return e == hipSuccess ? IAAT_OK : hip_fail(e, "iaat_gemm: scale launch");
+  }
+  const int64_t nsm = (m + kSuper - 1) / kSuper, nsn = (n + kSuper - 1) / kSuper;
+  if (nsm * nsn > 0x7fffffffLL)
+    return fail(IAAT_ERR_UNSUPPORTED, "iaat_gemm: %lld x %lld is too large for one launch",
+                (long long)m, (long long)n);
+  // grid.y = most blocks in any of the (at most four) super-block plans
+  const int lm = (int)(m - (nsm - 1) * kSuper), ln = (int)(n - (nsn - 1) * kSuper);
+  int maxb = 0;
+  const int ms[2] = {kSuper, lm}, ns[2] = {kSuper, ln};
+  for (int a = (nsm > 1 ? 0 : 1); a < 2; ++a)
+    for (int b = (nsn > 1 ? 0 : 1); b < 2; ++b) {
+      const int nb = (int)ctx->table[plan_index(layout, ms[a], ns[b])].nblk;
+      if (nb > maxb) maxb = nb;
+    }
+  dev::Prob P{A, B, C, (int)m, (int)n, (int)k, (int)lda, (int)ldb, (int)ldc, alpha, beta};
+  e = launch_gemm_f32(P, layout, ctx->table_dev, (int)nsm, (int)nsn, maxb, s);
+  return e == hipSuccess ? IAAT_OK : hip_fail(e, "iaat_gemm: launch");
+}
+
+int iaat_gemm_vbatched_device(iaat_ctx_t ctx, const iaat_problem* probs_dev, int64_t count,
+                              int prec, int32_t* status, iaat_stream_t stream) {
+  if (!ctx) return fail(-1, "iaat_gemm_vbatched_device: ctx is NULL");
+  if (count < 0 || count > 0x7fffffffLL)
+    return fail(-3, "iaat_gemm_vbatched_device: count=%lld", (long long)count);
+  if (count > 0 && !probs_dev) return fail(-2, "iaat_gemm_vbatched_device: probs is NULL");
+  if (prec != IAAT_PREC_F32) return fail(-4, "iaat_gemm_vbatched_device: prec=%d", prec);
+  if (count == 0) return IAAT_OK;
+  DeviceGuard g(ctx->device);
+  hipStream_t s = (hipStream_t)stream;
+  const uint64_t slot = ctx->slot_next.fetch_add(1) % kCtrSlots;
+  uint32_t* ctr = ctx->ctr_dev + slot * kCtrPerCall;
+  hipError_t e = launch_zero_u32(ctr, kCtrPerCall, s);
+  if (e != hipSuccess) return hip_fail(e, "iaat_gemm_vbatched_device: counter reset");
+  VbArgs a{probs_dev, count, status, ctx->table_dev, ctr};
+  const int grid = (int)(count < ctx->vb_grid ? count : ctx->vb_grid);
+  e = launch_vbatched_f32(a, grid, s);
+  return e == hipSuccess ? IAAT_OK : hip_fail(e, "iaat_gemm_vbatched_device: launch");
+}
+
+int iaat_gemm_vbatched(iaat_ctx_t ctx, const iaat_problem* probs_host, int64_t count, int prec,
+                       int32_t* status, iaat_stream_t stream) {
+  if (!ctx) return fail(-1, "iaat_gemm_vbatched: ctx is NULL");
+  if (count < 0 || count > 0x7fffffffLL)
+    return fail(-3, "iaat_gemm_vbatched: count=%lld", (long long)count);
+  if (count > 0 && !probs_host) return fail(-2, "iaat_gemm_vbatched: probs is NULL");
+  if (prec != IAAT_PREC_F32) return fail(-4, "iaat_gemm_vbatched: prec=%d", prec);
+  if (count == 0) return IAAT_OK;
+  DeviceGuard g(ctx->device);
+  std::lock_guard<std::mutex> lk(ctx->stage_mu);
+  hipError_t e = hipEventSynchronize(ctx->stage_evt);  // previous staged batch consumed
+  if (e != hipSuccess) return hip_fail(e, "iaat_gemm_vbatched: staging wait");
+  if (count > ctx->stage_cap) {
+    if (ctx->stage_host) (void)hipHostFree(ctx->stage_host);
+    if (ctx->stage_dev) (void)hipFree(ctx->stage_dev);
+    ctx->stage_host = nullptr;
+    ctx->stage_dev = nullptr;
+    ctx->stage_cap = 0;
+    const int64_t cap = count < 1024 ? 1024 : count;
+    if (hipHostMalloc(&ctx->stage_host, cap * sizeof(iaat_problem)) != hipSuccess ||
+        hipMalloc(&ctx->stage_dev, cap * sizeof(iaat_problem)) != hipSuccess)
+      return fail(IAAT_ERR_NOMEM, "iaat_gemm_vbatched: staging allocation of %lld failed",
+                  (long long)cap);
+    ctx->stage_cap = cap;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  memcpy(ctx->stage_host, probs_host, count * sizeof(iaat_problem));
+  e = hipMemcpyAsync(ctx->stage_dev, ctx->stage_host, count * sizeof(iaat_problem),
+                     hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return hip_fail(e, "iaat_gemm_vbatched: descriptor upload");
+  const int rc = iaat_gemm_vbatched_device(ctx, ctx->stage_dev, count, prec, status, stream);
+  if (rc != IAAT_OK) return rc;
+  e = hipEventRecord(ctx->stage_evt, s);
+  return e == hipSuccess ? IAAT_OK : hip_fail(e, "iaat_gemm_vbatched: event");
+}
+
+static int describe_plan(const PlanEntry& e, int m, int n, iaat_block* out, int cap) {
+  for (uint32_t b = 0; b < e.nblk && (int)b < cap; ++b) {
+    const int i0 = blk_i0(e.blk[b]), j0 = blk_j0(e.blk[b]), kid = blk_kid(e.blk[b]);
+    const KidInfo& k = kKids[kid];
+    out[b].i0 = i0;
+    out[b].j0 = j0;
+    out[b].rows = (i0 + k.rows < m ? i0 + k.rows : m) - i0;
+    out[b].cols = (j0 + k.cols < n ? j0 + k.cols : n) - j0;
+    out[b].kid = kid;
+  }
+  return (int)e.nblk;
+}
+
+int iaat_plan_query(iaat_ctx_t ctx, int layout, int m, int n, iaat_block* out, int cap) {
+  if (!ctx) return fail(-1, "iaat_plan_query: ctx is NULL");
+  if (layout < 0 || layout > 3) return fail(-2, "iaat_plan_query: layout=%d", layout);
+  if (m < 1 || m > kSuper) return fail(-3, "iaat_plan_query: m=%d", m);
+  if (n < 1 || n > kSuper) return fail(-4, "iaat_plan_query: n=%d", n);
+  if (cap < 0 || (cap > 0 && !out)) return fail(-6, "iaat_plan_query: cap=%d", cap);
+  return describe_plan(ctx->table[plan_index(layout, m, n)], m, n, out, cap);
+}
+
+int iaat_default_plan(int layout, int m, int n, iaat_block* out, int cap) {
+  if (layout < 0 || layout > 3) return fail(-1, "iaat_default_plan: layout=%d", layout);
+  if (m < 1 || m > kSuper) return fail(-2, "iaat_default_plan: m=%d", m);
+  if (n < 1 || n > kSuper) return fail(-3, "iaat_default_plan: n=%d", n);
+  if (cap < 0 || (cap > 0 && !out)) return fail(-5, "iaat_default_plan: cap=%d", cap);
+  return describe_plan(default_plan(layout, m, n), m, n, out, cap);
+}
+
+int iaat_family_size(void) { return IAAT_NUM_KIDS; }
+
+int iaat_family_info(int kid, int32_t* family, int32_t* p1, int32_t* p2, int32_t* block_rows,
+                     int32_t* block_cols) {
+  if (kid < 0 || kid >= IAAT_NUM_KIDS) return fail(-1, "iaat_family_info: kid=%d", kid);
+  const KidInfo& k = kKids[kid];
+  if (family) *family = k.fam;
+  if (p1) *p1 = k.p1;
+  if (p2) *p2 = k.p2;
+  if (block_rows) *block_rows = k.rows;
+  if (block_cols) *block_cols = k.cols;
+  return IAAT_OK;
+}
+
+int iaat_in_small_domain(int layout, int64_t m, int64_t n, int64_t k) {
+  if (layout < 0 || layout > 3) return fail(-1, "iaat_in_small_domain: layout=%d", layout);
+  if (m < 0) return fail(-2, "iaat_in_small_domain: m < 0");
+  if (n < 0) return fail(-3, "iaat_in_small_domain: n < 0");
+  if (k < 0) return fail(-4, "iaat_in_small_domain: k < 0");
+  return in_small_domain(layout, m, n, k) ? 1 : 0;
+}
+
+}  // extern "C"

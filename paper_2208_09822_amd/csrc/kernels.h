@@ -1,0 +1,44 @@
+// Host-side view of the device entry points (launch wrappers) of libiaat.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "iaat_internal.h"
+
+namespace iaat {
+namespace dev {
+// One FP32 problem (or super-block of one) as the block kernels see it;
+// alpha already includes any dequantisation factor.
+struct Prob {
+  const float* A;
+  const float* B;
+  float* C;
+  int m, n, k;
+  int lda, ldb, ldc;  // each < 2^31
+  float alpha, beta;
+};
+}  // namespace dev
+
+// Queue counters: 8 per batched call (one per XCD range), each on its own
+// 64-byte line.
+constexpr int kCtrStride = 16;
+constexpr int kCtrPerCall = 8 * kCtrStride;
+constexpr int kCtrSlots = 256;
+
+struct VbArgs {
+  const iaat_problem* probs;
+  int64_t count;
+  int32_t* status;
+  const PlanEntry* table;
+  uint32_t* ctr;
+};
+
+hipError_t launch_gemm_f32(const dev::Prob& P, int layout, const PlanEntry* table_dev, int nsm,
+                           int nsn, int max_blocks, hipStream_t stream);
+hipError_t launch_scale_f32(float* C, int m, int n, int ldc, float beta, hipStream_t stream);
+hipError_t launch_zero_u32(uint32_t* p, int n, hipStream_t stream);
+hipError_t launch_vbatched_f32(const VbArgs& a, int grid, hipStream_t stream);
+hipError_t vbatched_occupancy(int* blocks_per_cu);
+
+}  // namespace iaat

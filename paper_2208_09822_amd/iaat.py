@@ -1,0 +1,210 @@
+"""ctypes binding of libiaat (include/iaat.h).
+
+Argument marshalling only: every function has the name of the C entry point
+it calls, takes plain integers for device pointers and streams (for example
+``tensor.data_ptr()`` and ``torch.cuda.current_stream().cuda_stream``), and
+raises ``IaatError`` on a non-zero status.  All GEMM work runs in the HIP
+library; if ``libiaat.so`` has not been built, loading fails loudly.
+
+torch (when importable) is imported before the library is loaded so that the
+process has a single HIP runtime: torch's bundled ``libamdhip64.so.7`` then
+satisfies the library's dependency of the same soname.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+from typing import Optional
+
+import numpy as np
+
+try:  # share torch's HIP runtime when torch is used for memory and streams
+    import torch  # noqa: F401
+except Exception:  # pragma: no cover
+    torch = None
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libiaat.so")
+
+IAAT_OP_N, IAAT_OP_T = 0, 1
+IAAT_PREC_F32 = 0
+IAAT_OK = 0
+IAAT_ERR_HIP = -100
+IAAT_ERR_NOMEM = -101
+IAAT_ERR_TABLE = -102
+IAAT_ERR_UNSUPPORTED = -103
+
+FAMILY_NAMES = {0: "MFMA", 1: "ROWS", 2: "COLS", 3: "KRED"}
+
+# iaat_problem, 64 bytes
+PROBLEM_DTYPE = np.dtype([
+    ("A", "<u8"), ("B", "<u8"), ("C", "<u8"),
+    ("trans", "<i4"), ("m", "<i4"), ("n", "<i4"), ("k", "<i4"),
+    ("lda", "<i4"), ("ldb", "<i4"), ("ldc", "<i4"),
+    ("alpha", "<f4"), ("beta", "<f4"), ("ab_scale", "<f4"),
+])
+assert PROBLEM_DTYPE.itemsize == 64
+
+
+class IaatBlock(ctypes.Structure):
+    _fields_ = [("i0", ctypes.c_int32), ("j0", ctypes.c_int32), ("rows", ctypes.c_int32),
+                ("cols", ctypes.c_int32), ("kid", ctypes.c_int32)]
+
+
+class IaatError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("iaat error %d: %s" % (code, msg))
+        self.code = code
+
+
+_lib = None
+_lock = threading.Lock()
+
+
+def lib():
+    """The loaded library (raises if it has not been built)."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise RuntimeError("libiaat.so is not built (%s); run "
+                                   "`python -m paper_2208_09822_amd.build`" % LIB_PATH)
+            L = ctypes.CDLL(LIB_PATH)
+            i32, i64, f32, vp = ctypes.c_int, ctypes.c_int64, ctypes.c_float, ctypes.c_void_p
+            sig = {
+                "iaat_create": (i32, [ctypes.POINTER(vp), i32, ctypes.c_char_p]),
+                "iaat_destroy": (i32, [vp]),
+                "iaat_last_error": (ctypes.c_char_p, []),
+                "iaat_gemm": (i32, [vp, i32, i32, i64, i64, i64, f32, vp, i64, vp, i64, f32,
+                                    vp, i64, vp]),
+                "iaat_gemm_vbatched_device": (i32, [vp, vp, i64, i32, vp, vp]),
+                "iaat_gemm_vbatched": (i32, [vp, vp, i64, i32, vp, vp]),
+                "iaat_plan_query": (i32, [vp, i32, i32, i32, ctypes.POINTER(IaatBlock), i32]),
+                "iaat_default_plan": (i32, [i32, i32, i32, ctypes.POINTER(IaatBlock), i32]),
+                "iaat_family_size": (i32, []),
+                "iaat_family_info": (i32, [i32] + [ctypes.POINTER(ctypes.c_int32)] * 5),
+                "iaat_in_small_domain": (i32, [i32, i64, i64, i64]),
+            }
+            for name, (res, args) in sig.items():
+                fn = getattr(L, name)
+                fn.restype = res
+                fn.argtypes = args
+            _lib = L
+    return _lib
+
+
+def _check(rc: int) -> int:
+    if rc != IAAT_OK:
+        raise IaatError(rc, iaat_last_error())
+    return rc
+
+
+def iaat_last_error() -> str:
+    return (lib().iaat_last_error() or b"").decode()
+
+
+def iaat_create(device: int = 0, tile_table_path: Optional[str] = None) -> int:
+    h = ctypes.c_void_p()
+    p = tile_table_path.encode() if tile_table_path else None
+    _check(lib().iaat_create(ctypes.byref(h), int(device), p))
+    return h.value
+
+
+def iaat_destroy(ctx: int) -> None:
+    _check(lib().iaat_destroy(ctx))
+
+
+def iaat_gemm(ctx, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, stream=0) -> None:
+    _check(lib().iaat_gemm(ctx, int(ta), int(tb), int(m), int(n), int(k), float(alpha),
+                           A or None, int(lda), B or None, int(ldb), float(beta), C or None,
+                           int(ldc), stream or None))
+
+
+def iaat_gemm_vbatched_device(ctx, probs_dev, count, prec=IAAT_PREC_F32, status=0,
+                              stream=0) -> None:
+    _check(lib().iaat_gemm_vbatched_device(ctx, probs_dev or None, int(count), int(prec),
+                                           status or None, stream or None))
+
+
+def iaat_gemm_vbatched(ctx, probs_host: np.ndarray, count=None, prec=IAAT_PREC_F32, status=0,
+                       stream=0) -> None:
+    arr = np.ascontiguousarray(probs_host, dtype=PROBLEM_DTYPE)
+    count = len(arr) if count is None else int(count)
+    _check(lib().iaat_gemm_vbatched(ctx, arr.ctypes.data if count else None, count, int(prec),
+                                    status or None, stream or None))
+
+
+def _blocks(fn, *args, cap=16):
+    out = (IaatBlock * cap)()
+    n = fn(*args, out, cap)
+    if n < 0:
+        raise IaatError(n, iaat_last_error())
+    return [(b.i0, b.j0, b.rows, b.cols, b.kid) for b in out[:min(n, cap)]]
+
+
+def iaat_plan_query(ctx, layout, m, n):
+    """Blocks (i0, j0, rows, cols, kid) of the context's plan."""
+    return _blocks(lib().iaat_plan_query, ctx, int(layout), int(m), int(n))
+
+
+def iaat_default_plan(layout, m, n):
+    return _blocks(lib().iaat_default_plan, int(layout), int(m), int(n))
+
+
+def iaat_family_size() -> int:
+    return lib().iaat_family_size()
+
+
+def iaat_family_info(kid: int):
+    vals = [ctypes.c_int32() for _ in range(5)]
+    _check(lib().iaat_family_info(int(kid), *[ctypes.byref(v) for v in vals]))
+    fam, p1, p2, br, bc = (v.value for v in vals)
+    return {"family": FAMILY_NAMES[fam], "p1": p1, "p2": p2, "rows": br, "cols": bc}
+
+
+def iaat_in_small_domain(layout, m, n, k) -> bool:
+    rc = lib().iaat_in_small_domain(int(layout), int(m), int(n), int(k))
+    if rc < 0:
+        raise IaatError(rc, iaat_last_error())
+    return bool(rc)
+
+
+# ------------------------------------------------------------ marshalling
+
+def descriptors(ps, base_ptr: int, elem_bytes: int = 4, ab_scale=None) -> np.ndarray:
+    """iaat_problem array for a ProblemSet whose buffer sits in device memory
+    at ``base_ptr`` (element offsets scaled by ``elem_bytes``)."""
+    d = np.zeros(ps.count, dtype=PROBLEM_DTYPE)
+    d["A"] = base_ptr + ps.a_off.astype(np.uint64) * elem_bytes
+    d["B"] = base_ptr + ps.b_off.astype(np.uint64) * elem_bytes
+    d["C"] = base_ptr + ps.c_off.astype(np.uint64) * 4
+    d["trans"] = ps.trans
+    d["m"], d["n"], d["k"] = ps.m, ps.n, ps.k
+    d["lda"], d["ldb"], d["ldc"] = ps.lda, ps.ldb, ps.ldc
+    d["alpha"], d["beta"] = ps.alpha, ps.beta
+    d["ab_scale"] = 1.0 if ab_scale is None else ab_scale
+    return d
+
+
+class Context:
+    """Owns an iaat context (``with Context() as ctx: ...``)."""
+
+    def __init__(self, device: int = 0, tile_table_path: Optional[str] = None):
+        self.handle = iaat_create(device, tile_table_path)
+
+    def close(self):
+        if self.handle:
+            iaat_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
