@@ -1,0 +1,233 @@
+#!/usr/bin/env python3
+"""Benchmark of the batched small-GEMM path on one MI355X.
+
+Workload: 65,536 uneven FP32 problems C = alpha*op(A)*op(B) + beta*C;
+M, N, K uniform over 1..80, redrawn until cbrt(MNK) <= 80 (<= 32 for TN);
+layout uniform over NN/NT/TN/TT; entries U[-1,1]; alpha, beta U[-2,2];
+ld = stored row count; seeded synthetic data.  Operands and the descriptor
+array are resident in device memory before timing starts.
+
+One step = one replay of the graph-captured persistent launch
+(iaat_vbplan_launch) over the whole batch: on-device validation, tile-plan
+lookup, work queue, block kernels and epilogue.  GFLOP/s = sum 2MNK / t
+(the paper's Eq. 1).
+
+Also reported (not the headline value): the same batch through
+iaat_gemm_vbatched_device without a graph, through the host-descriptor form
+(PCIe copy of the descriptors included), through one iaat_gemm call per
+problem, and the FP64 oracle on the host's cores.
+
+    python bench.py [--gpus 1] [--steps 50] [--warmup 5]
+    python bench.py --profile           # short run for rocprofv3
+    python bench.py --calibrate-copy    # a plain 1 GiB device copy (counter scale)
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "vbatched small-GEMM GFLOP/s + %roofline vs per-call; p50/p99 serve latency"
+KERNEL = "vbatched_f32_kernel"
+
+
+def source_hash() -> str:
+    """Hash of the device sources: a stored counter profile applies only to
+    the kernel it was taken on."""
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2208_09822_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".h")):
+            h.update(name.encode())
+            h.update(open(os.path.join(csrc, name), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(workload: str):
+    """HBM bytes per launch from the committed counter profile, if it was
+    taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "vbatched_f32_kernel_uneven65536_counters.json")
+    try:
+        d = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if d.get("source_hash") != source_hash() or d.get("workload") != workload:
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--count", type=int, default=65536)
+    ap.add_argument("--profile", action="store_true",
+                    help="short run (5 steps) with no side measurements, for rocprofv3")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a 1 GiB device-to-device copy (counter calibration)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-percall", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU only (no multi-GPU path); "
+              "run with --gpus 1", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_2208_09822_amd import iaat, inputs
+
+    dev = torch.device("cuda:0")
+    if args.calibrate_copy:
+        n = (1 << 30) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": 1 << 30, "launches": 3}))
+        return 0
+
+    if args.profile:
+        args.steps, args.warmup = 5, 1
+        args.no_cpu_baseline = args.no_percall = True
+
+    t0 = time.time()
+    ps = inputs.uneven_batch(args.count)
+    workload = "uneven_vbatched_%d" % ps.count
+    flops = ps.flops()
+    alg_bytes = ps.algorithmic_bytes()
+    print("[bench] generated %d problems (%.3f GFLOP, %.3f GB algorithmic) in %.1fs"
+          % (ps.count, flops / 1e9, alg_bytes / 1e9, time.time() - t0), file=sys.stderr, flush=True)
+
+    buf = torch.from_numpy(ps.buf).to(dev)
+    desc = iaat.descriptors(ps, buf.data_ptr())
+    desc_dev = torch.from_numpy(desc.view(np.uint8)).to(dev)
+    stream = torch.cuda.current_stream(dev)
+    sp = stream.cuda_stream
+    ctx = iaat.Context(0)
+    plan = iaat.iaat_vbplan_create(ctx.handle, desc_dev.data_ptr(), ps.count)
+
+    # --- timed region: graph replays of the persistent batched launch
+    for _ in range(args.warmup):
+        iaat.iaat_vbplan_launch(plan, sp)
+    torch.cuda.synchronize(dev)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    ev[0].record(stream)
+    for s in range(args.steps):
+        iaat.iaat_vbplan_launch(plan, sp)
+        ev[s + 1].record(stream)
+    torch.cuda.synchronize(dev)
+    per = [ev[s].elapsed_time(ev[s + 1]) for s in range(args.steps)]
+    ms_total = ev[0].elapsed_time(ev[-1])
+    ms = ms_total / args.steps
+    value = flops / (ms * 1e-3) / 1e9
+    print("[bench] graph replay: %.1f us/step (median %.1f, min %.1f)"
+          % (ms * 1e3, float(np.median(per)) * 1e3, min(per) * 1e3), file=sys.stderr, flush=True)
+
+    achieved = alg_bytes / (ms * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": stored_traffic(workload),
+            "kernel": KERNEL, "algorithmic_bytes_per_launch": int(alg_bytes),
+            "avg_launch_us": round(ms * 1e3, 2)}
+
+    extra = {}
+    if not args.profile:
+        # the same batch without the graph, and with host-resident descriptors
+        def timed(fn, reps):
+            fn()
+            torch.cuda.synchronize(dev)
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            for _ in range(reps):
+                fn()
+            b.record(stream)
+            torch.cuda.synchronize(dev)
+            return a.elapsed_time(b) / reps
+
+        ms_dev = timed(lambda: iaat.iaat_gemm_vbatched_device(ctx.handle, desc_dev.data_ptr(),
+                                                              ps.count, stream=sp), 20)
+        ms_host = timed(lambda: iaat.iaat_gemm_vbatched(ctx.handle, desc, stream=sp), 10)
+        extra["device_descriptor_form"] = {"gflops": round(flops / ms_dev / 1e6, 1),
+                                           "us_per_call": round(ms_dev * 1e3, 1)}
+        extra["host_descriptor_form_pcie_inclusive"] = {
+            "gflops": round(flops / ms_host / 1e6, 1), "us_per_call": round(ms_host * 1e3, 1)}
+
+    if not args.no_percall:
+        # one iaat_gemm launch per problem, same problems, same stream
+        base = buf.data_ptr()
+        L = iaat.lib()
+        tr = ps.trans.tolist(); mm = ps.m.tolist(); nn = ps.n.tolist(); kk = ps.k.tolist()
+        al = ps.alpha.tolist(); be = ps.beta.tolist()
+        la = ps.lda.tolist(); lb = ps.ldb.tolist(); lc = ps.ldc.tolist()
+        ao = (base + 4 * ps.a_off).tolist(); bo = (base + 4 * ps.b_off).tolist()
+        co = (base + 4 * ps.c_off).tolist()
+        h = ctx.handle
+
+        def percall():
+            g = L.iaat_gemm
+            for q in range(ps.count):
+                t = tr[q]
+                g(h, t & 1, t >> 1, mm[q], nn[q], kk[q], al[q], ao[q], la[q], bo[q], lb[q],
+                  be[q], co[q], lc[q], sp)
+
+        percall()
+        torch.cuda.synchronize(dev)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        w0 = time.perf_counter()
+        a.record(stream)
+        percall()
+        b.record(stream)
+        torch.cuda.synchronize(dev)
+        wall = time.perf_counter() - w0
+        ms_pc = a.elapsed_time(b)
+        extra["per_call"] = {"gflops": round(flops / ms_pc / 1e6, 2),
+                             "us_per_problem": round(ms_pc * 1e3 / ps.count, 3),
+                             "launches": ps.count, "host_wall_s": round(wall, 3),
+                             "speedup_of_value": round(value / (flops / ms_pc / 1e6), 1)}
+        print("[bench] per-call: %.2f us/problem" % (ms_pc * 1e3 / ps.count), file=sys.stderr,
+              flush=True)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        cores = min(len(os.sched_getaffinity(0)), 16)
+        _, secs, _ = oracle.gemm_batch(ps, nthreads=cores)
+        cpu = {"value": round(flops / secs / 1e9, 3), "unit": "GFLOP/s", "cores": cores,
+               "kind": "oracle",
+               "sample": "the full %d-problem batch once, FP64 triple loop, %d threads, %.2f s"
+                         % (ps.count, cores, secs)}
+
+    iaat.iaat_vbplan_destroy(plan)
+    ctx.close()
+    out = {
+        "metric": METRIC, "value": round(value, 1), "unit": "GFLOP/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": workload, "problems": ps.count,
+                   "shapes": "M,N,K ~ U{1..80}, cbrt(MNK)<=80 (<=32 for TN)",
+                   "layouts": "NN/NT/TN/TT uniform", "values": "U[-1,1]",
+                   "scalars": "alpha,beta ~ U[-2,2]", "form": "iaat_vbplan_launch (hipGraph)",
+                   "gflop_per_step": round(flops / 1e9, 4),
+                   "algorithmic_gb_per_step": round(alg_bytes / 1e9, 4)},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    out.update(extra)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -125,8 +125,8 @@ typedef struct iaat_problem {
  * -9 lda, -10 B, -11 ldb, -13 C, -14 ldc).  An invalid problem is skipped;
  * the others are computed. */
 
-/* Computes every problem of a batch in one persistent launch (plus one tiny
- * counter-reset launch) on `stream`.  The descriptors are already in device
+/* Computes every problem of a batch in one persistent kernel launch on
+ * `stream`.  The descriptors are already in device
  * memory (`probs_dev`, count entries); validation, tile-plan lookup and the
  * work queue all run on the device, so the host does O(1) work.
  *   count >= 0 (arg 3); prec IAAT_PREC_F32 (arg 4); status: NULL or a device
@@ -146,6 +146,20 @@ int iaat_gemm_vbatched_device(iaat_ctx_t ctx, const iaat_problem* probs_dev, int
  * its capacity. */
 int iaat_gemm_vbatched(iaat_ctx_t ctx, const iaat_problem* probs_host, int64_t count,
                        int prec, int32_t* status, iaat_stream_t stream);
+
+/* Graph-replayed batch: captures the batched launch for the descriptor
+ * array `probs_dev` (count entries) into a HIP graph once; each
+ * iaat_vbplan_launch replays it on `stream`.  The descriptor array is read
+ * at every replay, so the caller may change its contents (pointers, sizes,
+ * scalars) between replays; its address and `count` are fixed.  The plan
+ * owns its own queue counters: replays of one plan must not overlap each
+ * other (launch them on one stream).  iaat_vbplan_create allocates and
+ * synchronises the device; launch does neither.
+ * create errors: -1 ctx, -2 probs_dev, -3 count, -4 prec, -6 out. */
+int iaat_vbplan_create(iaat_ctx_t ctx, const iaat_problem* probs_dev, int64_t count, int prec,
+                       int32_t* status, iaat_vbplan_t* out);
+int iaat_vbplan_launch(iaat_vbplan_t plan, iaat_stream_t stream);
+int iaat_vbplan_destroy(iaat_vbplan_t plan); /* NULL accepted */
 
 /* ------------------------------------------------------ introspection */
 

@@ -18,6 +18,14 @@
 
 using namespace iaat;
 
+struct iaat_vbplan {
+  iaat_ctx* ctx = nullptr;
+  uint32_t* ctr = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int64_t count = 0;
+};
+
 struct iaat_ctx {
   int device = 0;
   int num_cu = 0;
@@ -214,14 +222,80 @@ int iaat_gemm_vbatched_device(iaat_ctx_t ctx, const iaat_problem* probs_dev, int
   if (count == 0) return IAAT_OK;
   DeviceGuard g(ctx->device);
   hipStream_t s = (hipStream_t)stream;
+  // counters start at zero (iaat_create) and each launch leaves its slot at zero
   const uint64_t slot = ctx->slot_next.fetch_add(1) % kCtrSlots;
   uint32_t* ctr = ctx->ctr_dev + slot * kCtrPerCall;
-  hipError_t e = launch_zero_u32(ctr, kCtrPerCall, s);
-  if (e != hipSuccess) return hip_fail(e, "iaat_gemm_vbatched_device: counter reset");
   VbArgs a{probs_dev, count, status, ctx->table_dev, ctr};
   const int grid = (int)(count < ctx->vb_grid ? count : ctx->vb_grid);
-  e = launch_vbatched_f32(a, grid, s);
+  const hipError_t e = launch_vbatched_f32(a, grid, s);
   return e == hipSuccess ? IAAT_OK : hip_fail(e, "iaat_gemm_vbatched_device: launch");
+}
+
+int iaat_vbplan_create(iaat_ctx_t ctx, const iaat_problem* probs_dev, int64_t count, int prec,
+                       int32_t* status, iaat_vbplan_t* out) {
+  if (!ctx) return fail(-1, "iaat_vbplan_create: ctx is NULL");
+  if (count < 0 || count > 0x7fffffffLL)
+    return fail(-3, "iaat_vbplan_create: count=%lld", (long long)count);
+  if (count > 0 && !probs_dev) return fail(-2, "iaat_vbplan_create: probs is NULL");
+  if (prec != IAAT_PREC_F32) return fail(-4, "iaat_vbplan_create: prec=%d", prec);
+  if (!out) return fail(-6, "iaat_vbplan_create: out is NULL");
+  *out = nullptr;
+  DeviceGuard g(ctx->device);
+  iaat_vbplan* p = new iaat_vbplan;
+  p->ctx = ctx;
+  p->count = count;
+  hipStream_t cs = nullptr;
+  hipError_t e;
+  auto cleanup = [&](int rc) {
+    if (cs) (void)hipStreamDestroy(cs);
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->ctr) (void)hipFree(p->ctr);
+    delete p;
+    return rc;
+  };
+  const size_t cbytes = sizeof(uint32_t) * kCtrPerCall;
+  if (hipMalloc(&p->ctr, cbytes) != hipSuccess)
+    return cleanup(fail(IAAT_ERR_NOMEM, "iaat_vbplan_create: counter allocation"));
+  if ((e = hipMemset(p->ctr, 0, cbytes)) != hipSuccess ||
+      (e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking)) != hipSuccess ||
+      (e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+    return cleanup(hip_fail(e, "iaat_vbplan_create: capture setup"));
+  if (count > 0) {
+    VbArgs a{probs_dev, count, status, ctx->table_dev, p->ctr};
+    const int grid = (int)(count < ctx->vb_grid ? count : ctx->vb_grid);
+    e = launch_vbatched_f32(a, grid, cs);
+    if (e != hipSuccess) {
+      hipGraph_t tmp = nullptr;
+      (void)hipStreamEndCapture(cs, &tmp);
+      if (tmp) (void)hipGraphDestroy(tmp);
+      return cleanup(hip_fail(e, "iaat_vbplan_create: captured launch"));
+    }
+  }
+  if ((e = hipStreamEndCapture(cs, &p->graph)) != hipSuccess ||
+      (e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0)) != hipSuccess ||
+      (e = hipDeviceSynchronize()) != hipSuccess)
+    return cleanup(hip_fail(e, "iaat_vbplan_create: instantiate"));
+  (void)hipStreamDestroy(cs);
+  *out = p;
+  return IAAT_OK;
+}
+
+int iaat_vbplan_launch(iaat_vbplan_t plan, iaat_stream_t stream) {
+  if (!plan) return fail(-1, "iaat_vbplan_launch: plan is NULL");
+  DeviceGuard g(plan->ctx->device);
+  const hipError_t e = hipGraphLaunch(plan->exec, (hipStream_t)stream);
+  return e == hipSuccess ? IAAT_OK : hip_fail(e, "iaat_vbplan_launch");
+}
+
+int iaat_vbplan_destroy(iaat_vbplan_t plan) {
+  if (!plan) return IAAT_OK;
+  DeviceGuard g(plan->ctx->device);
+  if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
+  if (plan->graph) (void)hipGraphDestroy(plan->graph);
+  if (plan->ctr) (void)hipFree(plan->ctr);
+  delete plan;
+  return IAAT_OK;
 }
 
 int iaat_gemm_vbatched(iaat_ctx_t ctx, const iaat_problem* probs_host, int64_t count, int prec,

@@ -20,10 +20,11 @@ struct Prob {
 };
 }  // namespace dev
 
-// Queue counters: 8 per batched call (one per XCD range), each on its own
-// 64-byte line.
+// Queue counters: 8 per batched call (one per XCD range) plus one count of
+// finished wavefronts, each on its own 64-byte line.  The kernel leaves them
+// at zero when it ends.
 constexpr int kCtrStride = 16;
-constexpr int kCtrPerCall = 8 * kCtrStride;
+constexpr int kCtrPerCall = 9 * kCtrStride;
 constexpr int kCtrSlots = 256;
 
 struct VbArgs {

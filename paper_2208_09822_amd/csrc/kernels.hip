@@ -124,7 +124,9 @@ __device__ __forceinline__ void batched_problem(const VbArgs& a, int64_t q) {
 // ranges with one queue counter each (work-group w starts on range w % 8,
 // the XCD it is dispatched to); a wavefront pops problems from its range
 // until it is empty and then helps the other ranges in turn, so every
-// wavefront exits once all counters have passed their range ends.
+// wavefront exits once all counters have passed their range ends.  The last
+// wavefront to finish (counted on a ninth counter) sets all counters back to
+// zero for the next launch that uses this counter slot.
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4))) void vbatched_f32_kernel(VbArgs a) {
   const int home = (int)(blockIdx.x & 7);
   for (int rr = 0; rr < 8; ++rr) {
@@ -138,6 +140,17 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4))) void
       const int64_t q = lo + (int64_t)t;
       if (q >= hi) break;
       batched_problem(a, q);
+    }
+  }
+  if (lane() == 0) {
+    // acq_rel: this wavefront's last pop (whose result it has already used)
+    // is ordered before its count, and the resets after all counts
+    const uint32_t done = __hip_atomic_fetch_add(a.ctr + 8 * kCtrStride, 1u, __ATOMIC_ACQ_REL,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+    if (done == gridDim.x - 1) {  // every other wavefront has left its loop
+      for (int x = 0; x <= 8; ++x)
+        __hip_atomic_exchange(a.ctr + x * kCtrStride, 0u, __ATOMIC_RELAXED,
+                              __HIP_MEMORY_SCOPE_AGENT);
     }
   }
 }

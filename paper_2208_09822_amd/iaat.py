@@ -79,6 +79,9 @@ def lib():
                                     vp, i64, vp]),
                 "iaat_gemm_vbatched_device": (i32, [vp, vp, i64, i32, vp, vp]),
                 "iaat_gemm_vbatched": (i32, [vp, vp, i64, i32, vp, vp]),
+                "iaat_vbplan_create": (i32, [vp, vp, i64, i32, vp, ctypes.POINTER(vp)]),
+                "iaat_vbplan_launch": (i32, [vp, vp]),
+                "iaat_vbplan_destroy": (i32, [vp]),
                 "iaat_plan_query": (i32, [vp, i32, i32, i32, ctypes.POINTER(IaatBlock), i32]),
                 "iaat_default_plan": (i32, [i32, i32, i32, ctypes.POINTER(IaatBlock), i32]),
                 "iaat_family_size": (i32, []),
@@ -132,6 +135,21 @@ def iaat_gemm_vbatched(ctx, probs_host: np.ndarray, count=None, prec=IAAT_PREC_F
     count = len(arr) if count is None else int(count)
     _check(lib().iaat_gemm_vbatched(ctx, arr.ctypes.data if count else None, count, int(prec),
                                     status or None, stream or None))
+
+
+def iaat_vbplan_create(ctx, probs_dev, count, prec=IAAT_PREC_F32, status=0) -> int:
+    h = ctypes.c_void_p()
+    _check(lib().iaat_vbplan_create(ctx, probs_dev or None, int(count), int(prec), status or None,
+                                    ctypes.byref(h)))
+    return h.value
+
+
+def iaat_vbplan_launch(plan, stream=0) -> None:
+    _check(lib().iaat_vbplan_launch(plan, stream or None))
+
+
+def iaat_vbplan_destroy(plan) -> None:
+    _check(lib().iaat_vbplan_destroy(plan))
 
 
 def _blocks(fn, *args, cap=16):

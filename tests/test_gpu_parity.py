@@ -239,3 +239,55 @@ def test_full_size_uneven_batch(ctx):
     refs = oracle_all(ps, select=sel)
     for q in sel:
         check_problem(ps, out, int(q), refs[int(q)], exact=False)
+
+
+def test_graph_plan_replays_and_descriptor_updates(ctx):
+    """A captured batch replays correctly several times, with eager library
+    work between replays, and picks up descriptor edits made between them."""
+    ps = inputs.uneven_batch(2000, seed=91, integer=True)
+    ps.beta[:] = 0.0
+    ps.alpha[:] = 1.0
+    buf = torch.from_numpy(ps.buf).to(DEV)
+    desc = iaat.descriptors(ps, buf.data_ptr())
+    dd = torch.from_numpy(desc.view(np.uint8)).to(DEV)
+    plan = iaat.iaat_vbplan_create(ctx, dd.data_ptr(), ps.count)
+    try:
+        refs = oracle_all(ps)
+        other = inputs.uneven_batch(300, seed=92, integer=True)
+        for rep in range(3):
+            iaat.iaat_vbplan_launch(plan, stream())
+            torch.cuda.synchronize()
+            out = buf.cpu().numpy()
+            for q in range(0, ps.count, 7):
+                check_problem(ps, out, q, refs[q], exact=True)
+            run_vbatched(ctx, other)  # eager work in between
+        # change alpha to 2 in the device descriptors, replay
+        desc["alpha"][:] = 2.0
+        dd.copy_(torch.from_numpy(desc.view(np.uint8)))
+        iaat.iaat_vbplan_launch(plan, stream())
+        torch.cuda.synchronize()
+        out = buf.cpu().numpy()
+        for q in range(0, ps.count, 5):
+            assert fp32_equal(result_of(ps, out, q), 2.0 * refs[q])
+    finally:
+        iaat.iaat_vbplan_destroy(plan)
+
+
+def test_queue_counters_reset_across_many_calls(ctx):
+    """Each batched launch leaves its counter slot at zero: 260 calls (the
+    256-slot ring wraps) each add A*B once to C (alpha = beta = 1)."""
+    ps = inputs.uneven_batch(100, seed=93, integer=True)
+    ps.alpha[:] = 1.0
+    ps.beta[:] = 1.0
+    buf = torch.from_numpy(ps.buf).to(DEV)
+    dd = torch.from_numpy(iaat.descriptors(ps, buf.data_ptr()).view(np.uint8)).to(DEV)
+    reps = 260
+    for _ in range(reps):
+        iaat.iaat_gemm_vbatched_device(ctx, dd.data_ptr(), ps.count, stream=stream())
+    torch.cuda.synchronize()
+    out = buf.cpu().numpy()
+    ab = ps.subset(np.arange(ps.count))
+    ab.beta = np.zeros(ps.count, np.float32)
+    for q in range(ps.count):
+        expect = result_of(ps, ps.buf, q).astype(np.float64) + reps * oracle_one(ab, q)
+        assert fp32_equal(result_of(ps, out, q), expect), q
