@@ -133,8 +133,7 @@ typedef struct iaat_problem {
  *   array of count int32 (arg 5).
  * Problems must not write overlapping C.  Results are bitwise identical to
  * iaat_gemm on each problem (same tile plan, same block kernels).
- * Does not allocate.  At most 256 batched calls of one context may be in
- * flight at once (they share a ring of queue counters). */
+ * Does not allocate; keeps no state on the device between calls. */
 int iaat_gemm_vbatched_device(iaat_ctx_t ctx, const iaat_problem* probs_dev, int64_t count,
                               int prec, int32_t* status, iaat_stream_t stream);
 
@@ -151,10 +150,9 @@ int iaat_gemm_vbatched(iaat_ctx_t ctx, const iaat_problem* probs_host, int64_t c
  * array `probs_dev` (count entries) into a HIP graph once; each
  * iaat_vbplan_launch replays it on `stream`.  The descriptor array is read
  * at every replay, so the caller may change its contents (pointers, sizes,
- * scalars) between replays; its address and `count` are fixed.  The plan
- * owns its own queue counters: replays of one plan must not overlap each
- * other (launch them on one stream).  iaat_vbplan_create allocates and
- * synchronises the device; launch does neither.
+ * scalars) between replays; its address and `count` are fixed.
+ * iaat_vbplan_create allocates and synchronises the device; launch does
+ * neither.
  * create errors: -1 ctx, -2 probs_dev, -3 count, -4 prec, -6 out. */
 int iaat_vbplan_create(iaat_ctx_t ctx, const iaat_problem* probs_dev, int64_t count, int prec,
                        int32_t* status, iaat_vbplan_t* out);

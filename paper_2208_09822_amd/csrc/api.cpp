@@ -20,7 +20,6 @@ using namespace iaat;
 
 struct iaat_vbplan {
   iaat_ctx* ctx = nullptr;
-  uint32_t* ctr = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int64_t count = 0;
@@ -29,11 +28,10 @@ struct iaat_vbplan {
 struct iaat_ctx {
   int device = 0;
   int num_cu = 0;
-  int vb_grid = 0;
+  int vb_grid = 0;      // staged batched kernel: work-groups resident at once
+  int direct_grid = 0;  // direct batched kernel: wavefronts resident at once
   std::vector<PlanEntry> table;
   PlanEntry* table_dev = nullptr;
-  uint32_t* ctr_dev = nullptr;
-  std::atomic<uint64_t> slot_next{0};
   // staging for descriptors handed over in host memory
   std::mutex stage_mu;
   iaat_problem* stage_host = nullptr;
@@ -96,7 +94,6 @@ void free_ctx(iaat_ctx* c) {
   if (!c) return;
   DeviceGuard g(c->device);
   if (c->table_dev) (void)hipFree(c->table_dev);
-  if (c->ctr_dev) (void)hipFree(c->ctr_dev);
   if (c->stage_dev) (void)hipFree(c->stage_dev);
   if (c->stage_host) (void)hipHostFree(c->stage_host);
   if (c->stage_evt) (void)hipEventDestroy(c->stage_evt);
@@ -146,20 +143,20 @@ int iaat_create(iaat_ctx_t* out, int device, const char* tile_table_path) {
     free_ctx(c);
     return hip_fail(e, "iaat_create: device attribute");
   }
-  int per_cu = 0;
-  if ((e = vbatched_occupancy(&per_cu)) != hipSuccess || per_cu < 1) {
+  int per_cu = 0, direct_per_cu = 0;
+  if ((e = vbatched_occupancy(&per_cu, &direct_per_cu)) != hipSuccess || per_cu < 1 ||
+      direct_per_cu < 1) {
     free_ctx(c);
     return hip_fail(e, "iaat_create: occupancy");
   }
   c->vb_grid = per_cu * c->num_cu;
+  c->direct_grid = direct_per_cu * c->num_cu;
   const size_t tbytes = sizeof(PlanEntry) * c->table.size();
-  const size_t cbytes = sizeof(uint32_t) * kCtrPerCall * kCtrSlots;
-  if (hipMalloc(&c->table_dev, tbytes) != hipSuccess || hipMalloc(&c->ctr_dev, cbytes) != hipSuccess) {
+  if (hipMalloc(&c->table_dev, tbytes) != hipSuccess) {
     free_ctx(c);
     return fail(IAAT_ERR_NOMEM, "iaat_create: device allocation failed");
   }
   if ((e = hipMemcpy(c->table_dev, c->table.data(), tbytes, hipMemcpyHostToDevice)) != hipSuccess ||
-      (e = hipMemset(c->ctr_dev, 0, cbytes)) != hipSuccess ||
       (e = hipEventCreateWithFlags(&c->stage_evt, hipEventDisableTiming)) != hipSuccess ||
       (e = hipDeviceSynchronize()) != hipSuccess) {
     free_ctx(c);
@@ -222,12 +219,10 @@ int iaat_gemm_vbatched_device(iaat_ctx_t ctx, const iaat_problem* probs_dev, int
   if (count == 0) return IAAT_OK;
   DeviceGuard g(ctx->device);
   hipStream_t s = (hipStream_t)stream;
-  // counters start at zero (iaat_create) and each launch leaves its slot at zero
-  const uint64_t slot = ctx->slot_next.fetch_add(1) % kCtrSlots;
-  uint32_t* ctr = ctx->ctr_dev + slot * kCtrPerCall;
-  VbArgs a{probs_dev, count, status, ctx->table_dev, ctr};
+  VbArgs a{probs_dev, count, status, ctx->table_dev};
   const int grid = (int)(count < ctx->vb_grid ? count : ctx->vb_grid);
-  const hipError_t e = launch_vbatched_f32(a, grid, s);
+  const int dgrid = (int)((count + 63) / 64);  // one screening wavefront per 64 problems
+  const hipError_t e = launch_vbatched_f32(a, grid, dgrid, s);
   return e == hipSuccess ? IAAT_OK : hip_fail(e, "iaat_gemm_vbatched_device: launch");
 }
 
@@ -250,21 +245,17 @@ int iaat_vbplan_create(iaat_ctx_t ctx, const iaat_problem* probs_dev, int64_t co
     if (cs) (void)hipStreamDestroy(cs);
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
-    if (p->ctr) (void)hipFree(p->ctr);
     delete p;
     return rc;
   };
-  const size_t cbytes = sizeof(uint32_t) * kCtrPerCall;
-  if (hipMalloc(&p->ctr, cbytes) != hipSuccess)
-    return cleanup(fail(IAAT_ERR_NOMEM, "iaat_vbplan_create: counter allocation"));
-  if ((e = hipMemset(p->ctr, 0, cbytes)) != hipSuccess ||
-      (e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking)) != hipSuccess ||
+  if ((e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking)) != hipSuccess ||
       (e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal)) != hipSuccess)
     return cleanup(hip_fail(e, "iaat_vbplan_create: capture setup"));
   if (count > 0) {
-    VbArgs a{probs_dev, count, status, ctx->table_dev, p->ctr};
+    VbArgs a{probs_dev, count, status, ctx->table_dev};
     const int grid = (int)(count < ctx->vb_grid ? count : ctx->vb_grid);
-    e = launch_vbatched_f32(a, grid, cs);
+    const int dgrid = (int)((count + 63) / 64);
+    e = launch_vbatched_f32(a, grid, dgrid, cs);
     if (e != hipSuccess) {
       hipGraph_t tmp = nullptr;
       (void)hipStreamEndCapture(cs, &tmp);
@@ -293,7 +284,6 @@ int iaat_vbplan_destroy(iaat_vbplan_t plan) {
   DeviceGuard g(plan->ctx->device);
   if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
   if (plan->graph) (void)hipGraphDestroy(plan->graph);
-  if (plan->ctr) (void)hipFree(plan->ctr);
   delete plan;
   return IAAT_OK;
 }

@@ -20,26 +20,18 @@ struct Prob {
 };
 }  // namespace dev
 
-// Queue counters: 8 per batched call (one per XCD range) plus one count of
-// finished wavefronts, each on its own 64-byte line.  The kernel leaves them
-// at zero when it ends.
-constexpr int kCtrStride = 16;
-constexpr int kCtrPerCall = 9 * kCtrStride;
-constexpr int kCtrSlots = 256;
 
 struct VbArgs {
   const iaat_problem* probs;
   int64_t count;
   int32_t* status;
   const PlanEntry* table;
-  uint32_t* ctr;
 };
 
 hipError_t launch_gemm_f32(const dev::Prob& P, int layout, const PlanEntry* table_dev, int nsm,
                            int nsn, int max_blocks, hipStream_t stream);
 hipError_t launch_scale_f32(float* C, int m, int n, int ldc, float beta, hipStream_t stream);
-hipError_t launch_zero_u32(uint32_t* p, int n, hipStream_t stream);
-hipError_t launch_vbatched_f32(const VbArgs& a, int grid, hipStream_t stream);
-hipError_t vbatched_occupancy(int* blocks_per_cu);
+hipError_t launch_vbatched_f32(const VbArgs& a, int grid, int direct_grid, hipStream_t stream);
+hipError_t vbatched_occupancy(int* blocks_per_cu, int* direct_per_cu);
 
 }  // namespace iaat

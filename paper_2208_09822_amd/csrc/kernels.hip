@@ -1,11 +1,13 @@
 // Device entry points of libiaat: the per-call kernel (one problem, one
-// work-group per block of its tile plan), the persistent batched kernel
-// (wavefronts pop whole problems from a device work queue and run each
-// problem's kernel executing plan), and the quick-return scaling kernel.
+// work-group per block of its tile plan), the persistent batched kernels
+// (a producer wavefront stages batches of problems in LDS while consumer
+// wavefronts run their kernel executing plans; problems too large to stage
+// go to a direct kernel), and the quick-return scaling kernel.
 #include <hip/hip_runtime.h>
 
 #include "iaat_internal.h"
 #include "kernels.h"
+#include "lds_tiles.h"
 #include "tiles.h"
 
 namespace iaat {
@@ -90,67 +92,445 @@ __global__ __launch_bounds__(64) void scale_kernel(float* C, int m, int n, int l
   scale_columns(C, m, n, ldc, beta, (int)blockIdx.x, (int)gridDim.x);
 }
 
-__global__ void zero_u32_kernel(uint32_t* p, int n) {
-  const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-  if (i < n) p[i] = 0u;
+// ---------------------------------------------------------------------------
+// Batched path: one work-group of four wavefronts per problem.
+
+// Kernel family parameters, indexed by kid.
+__constant__ int kKidFam[IAAT_NUM_KIDS] = {
+#define IAAT_F(id, fam, p1, p2, br, bc) fam,
+    IAAT_FOR_EACH_KID(IAAT_F)
+#undef IAAT_F
+};
+__constant__ int kKidP1[IAAT_NUM_KIDS] = {
+#define IAAT_F(id, fam, p1, p2, br, bc) p1,
+    IAAT_FOR_EACH_KID(IAAT_F)
+#undef IAAT_F
+};
+__constant__ int kKidP2[IAAT_NUM_KIDS] = {
+#define IAAT_F(id, fam, p1, p2, br, bc) p2,
+    IAAT_FOR_EACH_KID(IAAT_F)
+#undef IAAT_F
+};
+
+// ---- batched kernel: staged batches --------------------------------------
+//
+// Work-groups of eight wavefronts, two per CU (each owns half of the LDS).
+// Problems are dealt to work-groups in windows of 16 consecutive problems
+// (window w to work-group w mod G).  Each iteration the work-group packs as
+// many of its next problems as fit into its staging buffer -- every
+// wavefront walks the same descriptors (16 per window, one per lane, with
+// their plan heads, read one window ahead) and copies its share of each
+// problem's A, B and (when beta != 0) C spans verbatim with memory-to-LDS
+// loads -- then waits once for all of them, and the eight wavefronts run the
+// batch's plan blocks round-robin from LDS and store C.  A barrier closes the
+// iteration because the buffer is refilled.  Problems that do not fit the
+// buffer are left to vbatched_direct_kernel; quick returns and status codes
+// are handled here.
+
+constexpr int kStage = 19456;        // floats of staging per work-group (>= one 80x80x80 problem)
+constexpr int kMaxBatch = 16;        // problems per batch
+constexpr int kMaxBatchBlocks = 64;  // plan blocks per batch
+constexpr int kWaves = 8;
+constexpr int kWin = 16;             // problems per descriptor window
+
+struct BatchProb {  // 64 bytes
+  float* C;
+  int la, lb, lc;  // float offsets into the staging buffer; lc < 0: C not staged
+  int m, n, k, lda, ldb, ldc;
+  float alpha, beta;
+  int trans;
+  int pad[2];
+};
+
+// One span copy of a batch: 16-byte-aligned source, staging offset (floats),
+// 16-byte units.
+struct CopyJob {
+  const float* src;
+  int dst, n4;
+};
+
+__shared__ __attribute__((aligned(16))) float g_stage[kStage];
+__shared__ BatchProb g_bprob[kMaxBatch];
+__shared__ uint32_t g_bblk[kMaxBatchBlocks];  // plan block | problem slot << 24
+__shared__ CopyJob g_copy[3 * kMaxBatch];
+__shared__ int g_bhead[4];                    // problems, blocks, copies, more-to-come
+
+// Staged size of one problem: A, B and (beta != 0) C spans, each widened to
+// whole 16-byte units around it.
+struct PcGeom {
+  int a_sh, b_sh, c_sh;
+  int a_n4, b_n4, c_n4;
+  bool fits;
+};
+
+__device__ __forceinline__ PcGeom pc_geom(const Prob& P, int ta, int tb) {
+  PcGeom g;
+  const int64_t span_a = (int64_t)P.lda * ((ta ? P.m : P.k) - 1) + (ta ? P.k : P.m);
+  const int64_t span_b = (int64_t)P.ldb * ((tb ? P.k : P.n) - 1) + (tb ? P.n : P.k);
+  const int64_t span_c = P.beta != 0.0f ? (int64_t)P.ldc * (P.n - 1) + P.m : 0;
+  g.a_sh = (int)(((uintptr_t)P.A & 15) >> 2);
+  g.b_sh = (int)(((uintptr_t)P.B & 15) >> 2);
+  g.c_sh = (int)(((uintptr_t)P.C & 15) >> 2);
+  const int64_t a_n4 = (g.a_sh + span_a + 3) >> 2, b_n4 = (g.b_sh + span_b + 3) >> 2;
+  const int64_t c_n4 = span_c > 0 ? (g.c_sh + span_c + 3) >> 2 : 0;
+  g.fits = P.m <= kSuper && P.n <= kSuper && narrow(P) && 4 * (a_n4 + b_n4 + c_n4) <= kStage;
+  g.a_n4 = g.fits ? (int)a_n4 : 0;
+  g.b_n4 = g.fits ? (int)b_n4 : 0;
+  g.c_n4 = g.fits ? (int)c_n4 : 0;
+  return g;
 }
 
-__device__ __forceinline__ void batched_problem(const VbArgs& a, int64_t q) {
-  const iaat_problem* d = a.probs + q;
-  const int trans = d->trans;
-  const int m = d->m, n = d->n, k = d->k;
-  const int lda = d->lda, ldb = d->ldb, ldc = d->ldc;
-  const float alpha = d->alpha * d->ab_scale, beta = d->beta;
-  const float* A = (const float*)d->A;
-  const float* B = (const float*)d->B;
-  float* C = d->C;
-  const int st = validate(trans, m, n, k, lda, ldb, ldc, alpha, A, B, C);
-  if (a.status != nullptr && lane() == 0) a.status[q] = st;
-  if (st != 0 || m == 0 || n == 0) return;
-  if (alpha == 0.0f || k == 0) {
-    scale_columns(C, m, n, ldc, beta, 0, 1);
-    return;
-  }
-  const Prob P{A, B, C, m, n, k, lda, ldb, ldc, alpha, beta};
-  switch (trans) {
-    case 0: solve_problem<0, 0>(P, a.table); break;
-    case 1: solve_problem<1, 0>(P, a.table); break;
-    case 2: solve_problem<0, 1>(P, a.table); break;
-    default: solve_problem<1, 1>(P, a.table); break;
-  }
+// Staged-operand dispatch: one routine per scheme, the kernel's sizes passed
+// as run-time values (each stored element gets the same arithmetic as in the
+// specialised direct kernels).
+template <int TA, int TB>
+__device__ __forceinline__ void run_block_lds(int kid, const LdsProb& P, int i0, int j0, int sync) {
+  const int fam = kKidFam[kid], p1 = kKidP1[kid], p2 = kKidP2[kid];
+  if (fam == FAM_MFMA) LdsMfma<TA, TB>::run(P, i0, j0, sync, p1, p2);
+  else if (fam == FAM_ROWS) LdsRows<TA, TB>::run(P, i0, j0, sync, p1);
+  else if (fam == FAM_COLS) LdsCols<TA, TB>::run(P, i0, j0, sync, p2);
+  else LdsKred<TA, TB>::run(P, i0, j0, sync, p1, p2);
 }
 
-// Persistent batched kernel.  The problem list is cut into 8 contiguous
-// ranges with one queue counter each (work-group w starts on range w % 8,
-// the XCD it is dispatched to); a wavefront pops problems from its range
-// until it is empty and then helps the other ranges in turn, so every
-// wavefront exits once all counters have passed their range ends.  The last
-// wavefront to finish (counted on a ninth counter) sets all counters back to
-// zero for the next launch that uses this counter slot.
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4))) void vbatched_f32_kernel(VbArgs a) {
-  const int home = (int)(blockIdx.x & 7);
-  for (int rr = 0; rr < 8; ++rr) {
-    const int x = (home + rr) & 7;
-    const int64_t lo = a.count * x / 8, hi = a.count * (x + 1) / 8;
-    if (lo >= hi) continue;
-    for (;;) {
-      uint32_t t = 0;
-      if (lane() == 0) t = atomicAdd(a.ctr + x * kCtrStride, 1u);
-      t = __builtin_amdgcn_readfirstlane(t);
-      const int64_t q = lo + (int64_t)t;
-      if (q >= hi) break;
-      batched_problem(a, q);
+// This work-group's share of a span copy: all 512 threads take consecutive
+// 16-byte units (each lane's 16 bytes land at its wavefront's LDS base + 16 *
+// lane).
+__device__ __forceinline__ void stage_span_group(const float* g16, lds_f* dst, int n4) {
+  typedef __attribute__((address_space(1))) const void gvoid;
+  typedef __attribute__((address_space(3))) void lvoid;
+  const int l = lane();
+  for (int t = (int)threadIdx.x; t < n4; t += 64 * kWaves)
+    __builtin_amdgcn_global_load_lds((gvoid*)(g16 + 4 * t), (lvoid*)(dst + 4 * (t - l)), 16, 0, 0);
+}
+
+__device__ __forceinline__ int rdl(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+__device__ __forceinline__ uint32_t rdl(uint32_t v, int l) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, l);
+}
+
+// kWin descriptors (lane l < kWin holds problem base + l) and plan heads.
+struct DescWindow {
+  uint32_t w[16];  // the iaat_problem words
+  uint32_t nblk, b0, b1, b2, b3;
+};
+
+__device__ __forceinline__ void window_load(DescWindow& W, const VbArgs& a, int64_t base) {
+  const int64_t q = min(base + (lane() & (kWin - 1)), a.count - 1);
+  const uint32_t* src = reinterpret_cast<const uint32_t*>(a.probs + q);
+#pragma unroll
+  for (int i = 0; i < 16; ++i) W.w[i] = src[i];
+}
+
+__device__ __forceinline__ void window_load_plan(DescWindow& W, const PlanEntry* table) {
+  const int trans = (int)W.w[6];
+  const int m = min(max((int)W.w[7], 1), kSuper), n = min(max((int)W.w[8], 1), kSuper);
+  const PlanEntry* e = table + plan_index(trans & 3, m, n);
+  W.nblk = e->nblk;
+  W.b0 = e->blk[0];
+  W.b1 = e->blk[1];
+  W.b2 = e->blk[2];
+  W.b3 = e->blk[3];
+}
+
+// The problem held by this lane / by lane `l` of a window.
+__device__ __forceinline__ Prob lane_prob(const DescWindow& W) {
+  const uint64_t A = ((uint64_t)W.w[1] << 32) | W.w[0];
+  const uint64_t B = ((uint64_t)W.w[3] << 32) | W.w[2];
+  const uint64_t C = ((uint64_t)W.w[5] << 32) | W.w[4];
+  return Prob{(const float*)A, (const float*)B, (float*)C, (int)W.w[7], (int)W.w[8], (int)W.w[9],
+              (int)W.w[10], (int)W.w[11], (int)W.w[12],
+              __builtin_bit_cast(float, W.w[13]) * __builtin_bit_cast(float, W.w[15]),
+              __builtin_bit_cast(float, W.w[14])};
+}
+
+__device__ __forceinline__ Prob lane_prob_of(const DescWindow& W, int l) {
+  const uint64_t A = ((uint64_t)rdl(W.w[1], l) << 32) | rdl(W.w[0], l);
+  const uint64_t B = ((uint64_t)rdl(W.w[3], l) << 32) | rdl(W.w[2], l);
+  const uint64_t C = ((uint64_t)rdl(W.w[5], l) << 32) | rdl(W.w[4], l);
+  return Prob{(const float*)A, (const float*)B, (float*)C, (int)rdl(W.w[7], l), (int)rdl(W.w[8], l),
+              (int)rdl(W.w[9], l), (int)rdl(W.w[10], l), (int)rdl(W.w[11], l),
+              (int)rdl(W.w[12], l),
+              __builtin_bit_cast(float, rdl(W.w[13], l)) * __builtin_bit_cast(float, rdl(W.w[15], l)),
+              __builtin_bit_cast(float, rdl(W.w[14], l))};
+}
+
+// Per-lane view of one problem of the current window (lane l < kWin holds
+// problem win*kWin + l): its class and, when it is staged, its copy jobs.
+enum { CLS_NONE = 0, CLS_QUICK = 1, CLS_STAGE = 2, CLS_DIRECT = 3 };
+
+struct LaneProb {
+  int cls, st, need, nbp;
+  PcGeom g;
+};
+
+__device__ __forceinline__ LaneProb classify(const DescWindow& W, bool valid_lane) {
+  LaneProb r{};
+  const Prob P = lane_prob(W);
+  const int trans = (int)W.w[6];
+  r.st = validate(trans, P.m, P.n, P.k, P.lda, P.ldb, P.ldc, P.alpha, P.A, P.B, P.C);
+  if (!valid_lane || r.st != 0 || P.m == 0 || P.n == 0) {
+    r.cls = CLS_NONE;
+  } else if (P.alpha == 0.0f || P.k == 0) {
+    r.cls = CLS_QUICK;
+  } else {
+    r.g = pc_geom(P, trans & 1, trans >> 1);
+    r.cls = r.g.fits ? CLS_STAGE : CLS_DIRECT;
+    r.need = r.g.fits ? 4 * (r.g.a_n4 + r.g.b_n4 + r.g.c_n4) : 0;
+    r.nbp = r.g.fits ? (int)W.nblk : 0;
+  }
+  return r;
+}
+
+// Inclusive prefix sum over the first kWin lanes.
+__device__ __forceinline__ int scan16(int v) {
+  const int l = lane();
+#pragma unroll
+  for (int off = 1; off < kWin; off <<= 1) {
+    const int u = __shfl_up(v, off, 64);
+    if (l >= off) v += u;
+  }
+  return v;
+}
+
+// Wavefront 0 packs the next batch: problems of this work-group's windows,
+// in order, while they fit.  All bookkeeping is per lane (one problem per
+// lane) plus prefix sums, then every taken lane writes its own table
+// entries; so the cost per batch does not grow with the number of problems.
+__device__ __forceinline__ void pack_batch(const VbArgs& a, int64_t G, int64_t nwin, int64_t& win,
+                                           int& i, DescWindow& W0, DescWindow& W1, bool& plan1,
+                                           LaneProb& LP) {
+  const int l = lane();
+  int used = 0, np = 0, nb = 0, nc = 0;
+  bool more = true;
+  for (;;) {
+    if (i == kWin) {  // window done: advance (the next window was prefetched)
+      win += G;
+      if (win >= nwin) {
+        more = false;
+        break;
+      }
+      if (!plan1) window_load_plan(W1, a.table);
+      W0 = W1;
+      plan1 = false;
+      i = 0;
+      if (win + G < nwin) window_load(W1, a, (win + G) * kWin);
+      LP = classify(W0, l < kWin && win * kWin + l < a.count);
     }
+    // candidates: lanes >= i that are staged
+    const bool cand = l >= i && l < kWin && LP.cls == CLS_STAGE;
+    const int c_need = scan16(cand ? LP.need : 0);
+    const int c_blk = scan16(cand ? LP.nbp : 0);
+    const int c_cnt = scan16(cand ? 1 : 0);
+    const bool fits = used + c_need <= kStage && nb + c_blk <= kMaxBatchBlocks && np + c_cnt <= kMaxBatch;
+    // first staged lane that does not fit ends this batch
+    const uint64_t stop = __ballot(cand && !fits) & 0xffffull;
+    const int end = stop ? __builtin_ctzll(stop) : kWin;
+    const bool take = l >= i && l < end;  // consumed by this batch
+    const int64_t q = win * kWin + l;
+    if (take && LP.cls != CLS_NONE && a.status != nullptr) a.status[q] = 0;
+    if (take && LP.cls == CLS_NONE && l < kWin && q < a.count && a.status != nullptr) a.status[q] = LP.st;
+    // quick returns (beta * C), one after another
+    uint64_t qm = __ballot(take && LP.cls == CLS_QUICK);
+    while (qm) {
+      const int ql = __builtin_ctzll(qm);
+      qm &= qm - 1;
+      const Prob P = lane_prob_of(W0, ql);
+      scale_columns(P.C, P.m, P.n, P.ldc, P.beta, 0, 1);
+    }
+    if (take && LP.cls == CLS_STAGE) {
+      const int slot = np + c_cnt - 1;
+      const int off = used + c_need - LP.need;  // staging offset of this problem
+      const Prob P = lane_prob(W0);
+      const PcGeom& g = LP.g;
+      BatchProb& bp = g_bprob[slot];
+      bp.C = P.C;
+      bp.la = off + g.a_sh;
+      bp.lb = off + 4 * g.a_n4 + g.b_sh;
+      bp.lc = g.c_n4 > 0 ? off + 4 * (g.a_n4 + g.b_n4) + g.c_sh : -1;
+      bp.m = P.m;
+      bp.n = P.n;
+      bp.k = P.k;
+      bp.lda = P.lda;
+      bp.ldb = P.ldb;
+      bp.ldc = P.ldc;
+      bp.alpha = P.alpha;
+      bp.beta = P.beta;
+      bp.trans = (int)W0.w[6];
+      g_copy[3 * slot] = CopyJob{P.A - g.a_sh, off, g.a_n4};
+      g_copy[3 * slot + 1] = CopyJob{P.B - g.b_sh, off + 4 * g.a_n4, g.b_n4};
+      g_copy[3 * slot + 2] = CopyJob{P.C - g.c_sh, off + 4 * (g.a_n4 + g.b_n4), g.c_n4};
+      const int b0 = nb + c_blk - LP.nbp;
+      const uint32_t tag = (uint32_t)slot << 24;
+      if (LP.nbp > 0) g_bblk[b0] = W0.b0 | tag;
+      if (LP.nbp > 1) g_bblk[b0 + 1] = W0.b1 | tag;
+      if (LP.nbp > 2) g_bblk[b0 + 2] = W0.b2 | tag;
+      if (LP.nbp > 3) g_bblk[b0 + 3] = W0.b3 | tag;
+      if (LP.nbp > 4) {
+        const PlanEntry* e = a.table + plan_index((int)W0.w[6] & 3, P.m, P.n);
+        for (int b = 4; b < LP.nbp; ++b) g_bblk[b0 + b] = e->blk[b] | tag;
+      }
+    }
+    // totals of the taken lanes (lane end-1's prefix values; 0 if none)
+    const int last = end - 1;
+    const int t_need = last >= i ? __builtin_amdgcn_readlane(c_need, last) : 0;
+    const int t_blk = last >= i ? __builtin_amdgcn_readlane(c_blk, last) : 0;
+    const int t_cnt = last >= i ? __builtin_amdgcn_readlane(c_cnt, last) : 0;
+    used += t_need;
+    nb += t_blk;
+    np += t_cnt;
+    nc = 3 * np;
+    i = end;
+    if (end < kWin) break;  // a problem did not fit: this batch is full
   }
-  if (lane() == 0) {
-    // acq_rel: this wavefront's last pop (whose result it has already used)
-    // is ordered before its count, and the resets after all counts
-    const uint32_t done = __hip_atomic_fetch_add(a.ctr + 8 * kCtrStride, 1u, __ATOMIC_ACQ_REL,
-                                                 __HIP_MEMORY_SCOPE_AGENT);
-    if (done == gridDim.x - 1) {  // every other wavefront has left its loop
-      for (int x = 0; x <= 8; ++x)
-        __hip_atomic_exchange(a.ctr + x * kCtrStride, 0u, __ATOMIC_RELAXED,
-                              __HIP_MEMORY_SCOPE_AGENT);
+  if (l == 0) {
+    g_bhead[0] = np;
+    g_bhead[1] = nb;
+    g_bhead[2] = nc;
+    g_bhead[3] = more ? 1 : 0;
+  }
+}
+
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 4)))
+void vbatched_f32_kernel(VbArgs a) {
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));  // wave-uniform
+  const int64_t G = gridDim.x;
+  const int64_t nwin = (a.count + kWin - 1) / kWin;
+  int64_t win = blockIdx.x;  // this work-group's current window (wavefront 0's state)
+  if (win >= nwin) return;
+  DescWindow W0, W1;
+  LaneProb LP{};
+  bool plan1 = false;
+  int i = 0;
+  if (w == 0) {
+    window_load(W0, a, win * kWin);
+    window_load_plan(W0, a.table);
+    if (win + G < nwin) window_load(W1, a, (win + G) * kWin);
+    LP = classify(W0, lane() < kWin && win * kWin + lane() < a.count);
+  }
+  lds_f* stage = (lds_f*)g_stage;
+  for (;;) {
+    if (w == 0) pack_batch(a, G, nwin, win, i, W0, W1, plan1, LP);
+    __syncthreads();  // batch tables visible
+    const int np = __builtin_amdgcn_readfirstlane(g_bhead[0]);
+    const int nb = __builtin_amdgcn_readfirstlane(g_bhead[1]);
+    const int nc = __builtin_amdgcn_readfirstlane(g_bhead[2]);
+    const int more = __builtin_amdgcn_readfirstlane(g_bhead[3]);
+    if (np > 0) {
+      // every wavefront issues its share of every copy, then one wait
+      for (int c = 0; c < nc; ++c) {
+        const CopyJob& cj = g_copy[c];
+        const uint64_t sp = (uint64_t)cj.src;
+        const uint64_t su = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(sp >> 32)) << 32) |
+                            (uint32_t)__builtin_amdgcn_readfirstlane((int)sp);
+        stage_span_group((const float*)su, stage + __builtin_amdgcn_readfirstlane(cj.dst),
+                         __builtin_amdgcn_readfirstlane(cj.n4));
+      }
+      staged_barrier();
+      // blocks w, w + 8, ... of the batch
+      for (int bi = w; bi < nb; bi += kWaves) {
+        const uint32_t e = (uint32_t)__builtin_amdgcn_readfirstlane((int)g_bblk[bi]);
+        const BatchProb& bp = g_bprob[e >> 24];
+        const int lc = __builtin_amdgcn_readfirstlane(bp.lc);
+        const uint64_t cp = (uint64_t)bp.C;
+        const uint64_t cu = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(cp >> 32)) << 32) |
+                            (uint32_t)__builtin_amdgcn_readfirstlane((int)cp);
+        const LdsProb L{stage + __builtin_amdgcn_readfirstlane(bp.la),
+                        stage + __builtin_amdgcn_readfirstlane(bp.lb), lc >= 0 ? stage + lc : nullptr,
+                        (float*)cu, __builtin_amdgcn_readfirstlane(bp.m),
+                        __builtin_amdgcn_readfirstlane(bp.n), __builtin_amdgcn_readfirstlane(bp.k),
+                        __builtin_amdgcn_readfirstlane(bp.lda), __builtin_amdgcn_readfirstlane(bp.ldb),
+                        __builtin_amdgcn_readfirstlane(bp.ldc),
+                        __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, bp.alpha))),
+                        __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, bp.beta)))};
+        const int trans = __builtin_amdgcn_readfirstlane(bp.trans);
+        const int kid = blk_kid(e), i0 = blk_i0(e), j0 = blk_j0(e);
+        switch (trans) {
+          case 0: run_block_lds<0, 0>(kid, L, i0, j0, SYNC_NONE); break;
+          case 1: run_block_lds<1, 0>(kid, L, i0, j0, SYNC_NONE); break;
+          case 2: run_block_lds<0, 1>(kid, L, i0, j0, SYNC_NONE); break;
+          default: run_block_lds<1, 1>(kid, L, i0, j0, SYNC_NONE); break;
+        }
+      }
+    }
+    if (!more) break;
+    __syncthreads();  // the buffer and the batch tables are refilled next
+  }
+}
+
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ float unif(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ const void* unip(const void* p) {
+  const uint64_t v = (uint64_t)p;
+  return (const void*)(((uint64_t)(uint32_t)uni((int)(v >> 32)) << 32) | (uint32_t)uni((int)v));
+}
+
+// A problem that does not fit the staging buffer, on one wavefront: every
+// super-block, every block of its plan, operands read straight from memory.
+// A separate function per layout (this path is rare; keeping it out of line
+// keeps the batched kernels small).  Arguments are wave-uniform and are made
+// scalar again on entry.
+template <int TA, int TB>
+__device__ __noinline__ void direct_problem_fn(const float* A, const float* B, float* C, int m, int n,
+                                               int k, int lda, int ldb, int ldc, float alpha,
+                                               float beta, const PlanEntry* table) {
+  const Prob P{(const float*)unip(A), (const float*)unip(B), (float*)unip(C), uni(m), uni(n), uni(k),
+               uni(lda), uni(ldb), uni(ldc), unif(alpha), unif(beta)};
+  solve_problem<TA, TB>(P, (const PlanEntry*)unip(table));
+}
+
+template <int TA, int TB>
+__device__ __forceinline__ void direct_problem(const Prob& P, const PlanEntry* __restrict__ table) {
+  direct_problem_fn<TA, TB>(P.A, P.B, P.C, P.m, P.n, P.k, P.lda, P.ldb, P.ldc, P.alpha, P.beta, table);
+}
+
+__device__ __forceinline__ bool load_problem(const VbArgs& a, int64_t q, Prob& P, int& trans,
+                                             int& st) {
+  const iaat_problem* d = a.probs + q;
+  trans = d->trans;
+  P.m = d->m;
+  P.n = d->n;
+  P.k = d->k;
+  P.lda = d->lda;
+  P.ldb = d->ldb;
+  P.ldc = d->ldc;
+  P.alpha = d->alpha * d->ab_scale;
+  P.beta = d->beta;
+  P.A = (const float*)d->A;
+  P.B = (const float*)d->B;
+  P.C = d->C;
+  st = validate(trans, P.m, P.n, P.k, P.lda, P.ldb, P.ldc, P.alpha, P.A, P.B, P.C);
+  return st == 0 && P.m > 0 && P.n > 0;
+}
+
+// Batched problems that do not fit the staging buffer.  Wavefront w of the
+// grid screens problems 64w .. 64w + 63, one per lane (valid, needs A*B, and
+// fails the same staging test as vbatched_f32_kernel, so every problem is
+// computed by exactly one of the two kernels), then computes the ones found,
+// one after another; most wavefronts find none and exit after one load.
+__global__ __launch_bounds__(64) void vbatched_direct_kernel(VbArgs a) {
+  const int64_t base = (int64_t)blockIdx.x * 64;
+  const int64_t q = base + lane();
+  bool need = false;
+  if (q < a.count) {
+    Prob P;
+    int trans, st;
+    if (load_problem(a, q, P, trans, st) && P.alpha != 0.0f && P.k != 0)
+      need = !pc_geom(P, trans & 1, trans >> 1).fits;
+  }
+  uint64_t mask = __ballot(need);
+  while (mask) {
+    const int l = __builtin_ctzll(mask);
+    mask &= mask - 1;
+    Prob P;
+    int trans, st;
+    load_problem(a, base + l, P, trans, st);
+    switch (trans) {
+      case 0: direct_problem<0, 0>(P, a.table); break;
+      case 1: direct_problem<1, 0>(P, a.table); break;
+      case 2: direct_problem<0, 1>(P, a.table); break;
+      default: direct_problem<1, 1>(P, a.table); break;
     }
   }
 }
@@ -177,18 +557,18 @@ hipError_t launch_scale_f32(float* C, int m, int n, int ldc, float beta, hipStre
   return hipGetLastError();
 }
 
-hipError_t launch_zero_u32(uint32_t* p, int n, hipStream_t stream) {
-  hipLaunchKernelGGL(dev::zero_u32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, p, n);
+hipError_t launch_vbatched_f32(const VbArgs& a, int grid, int direct_grid, hipStream_t stream) {
+  hipLaunchKernelGGL(dev::vbatched_f32_kernel, dim3((unsigned)grid), dim3(512), 0, stream, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(dev::vbatched_direct_kernel, dim3((unsigned)direct_grid), dim3(64), 0, stream, a);
   return hipGetLastError();
 }
 
-hipError_t launch_vbatched_f32(const VbArgs& a, int grid, hipStream_t stream) {
-  hipLaunchKernelGGL(dev::vbatched_f32_kernel, dim3((unsigned)grid), dim3(64), 0, stream, a);
-  return hipGetLastError();
-}
-
-hipError_t vbatched_occupancy(int* blocks_per_cu) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, dev::vbatched_f32_kernel, 64, 0);
+hipError_t vbatched_occupancy(int* blocks_per_cu, int* direct_per_cu) {
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, dev::vbatched_f32_kernel, 512, 0);
+  if (e != hipSuccess) return e;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(direct_per_cu, dev::vbatched_direct_kernel, 64, 0);
 }
 
 }  // namespace iaat

@@ -10,9 +10,12 @@
 //   * m <= 8: one row strip of height m, cut into 64-column pieces;
 //   * n <= 8: one column strip of width n, cut into 64-row pieces;
 //   * otherwise matrix-core tiles: ceil(m/16) x ceil(n/16) 16x16 tiles,
-//     grouped into blocks of at most 3 x 3 tiles with the groups balanced
-//     (5 -> 3+2, 4 -> 2+2), which keeps sum(m_i + n_i) minimal among
-//     groupings with that block bound.
+//     split into at most two balanced groups per dimension (1 -> 1,
+//     2 -> 1+1, 3 -> 2+1, 4 -> 2+2, 5 -> 3+2), so a sub-problem has at most
+//     four blocks of at most 3 x 3 tiles: one block per wavefront of the
+//     batched kernel's work-group, which reads A and B from LDS, so the
+//     extra block edges (sum(m_i + n_i) grows with the block count) cost
+//     LDS reads rather than memory traffic.
 // The plan depends only on (layout, m, n), never on K: every candidate
 // moves K * sum(m_i + n_i) operand values, so K does not change the order.
 // The autotuner may replace any plan with one it measured faster; every plan
@@ -36,9 +39,9 @@ static int find_kid(int fam, int p1, int p2) {
   return -1;
 }
 
-// Split t tiles into groups of at most 3, as evenly as possible.
+// Split t <= 6 tiles into at most two groups, as evenly as possible.
 static int split_tiles(int t, int* sizes) {
-  const int g = (t + 2) / 3;
+  const int g = t > 1 ? 2 : 1;
   for (int i = 0; i < g; ++i) sizes[i] = t / g + (i < t % g ? 1 : 0);
   return g;
 }

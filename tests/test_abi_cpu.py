@@ -81,30 +81,19 @@ def test_default_plans_cover_exactly(layout):
             assert (cover == 1).all(), (layout, m, n, blocks)
 
 
-def test_default_plan_is_k_independent_and_minimal_for_mfma():
-    """Matrix-core plans group ceil(m/16) x ceil(n/16) tiles into at most 3 x 3
-    blocks; among such groupings the balanced one minimises sum(m_i + n_i)
-    (the load-count principle of Section V-A) -- checked by brute force over
-    all groupings into at most two groups per dimension."""
-    for m in range(9, 81, 7):
-        for n in range(9, 81, 5):
-            blocks = iaat.iaat_default_plan(0, m, n)
-            s = sum(r + c for (_, _, r, c, _) in blocks)
-            tm, tn = -(-m // 16), -(-n // 16)
-
-            def groupings(t):
-                if t <= 3:
-                    yield [t]
-                for a in range(1, 4):
-                    if 0 < t - a <= 3:
-                        yield [a, t - a]
-
-            best = None
-            for gm in groupings(tm):
-                for gn in groupings(tn):
-                    rows = [min(16 * g, m - 16 * sum(gm[:i])) for i, g in enumerate(gm)]
-                    cols = [min(16 * g, n - 16 * sum(gn[:i])) for i, g in enumerate(gn)]
-                    cost = sum(r + c for r in rows for c in cols)
-                    if len(gm) * len(gn) == len(blocks):
-                        best = cost if best is None else min(best, cost)
-            assert s == best, (m, n, s, best)
+def test_default_matrix_core_plans_use_at_most_four_balanced_blocks():
+    """Matrix-core plans split ceil(m/16) x ceil(n/16) tiles into at most two
+    balanced groups per dimension (at most 3 tiles each), one block per
+    wavefront of a four-wavefront work-group."""
+    for layout in range(4):
+        for m in range(9, 81):
+            for n in range(9, 81):
+                blocks = iaat.iaat_default_plan(layout, m, n)
+                infos = [iaat.iaat_family_info(b[4]) for b in blocks]
+                assert all(i["family"] == "MFMA" for i in infos)
+                tm, tn = -(-m // 16), -(-n // 16)
+                gm = sorted({i["p1"] for i in infos}, reverse=True)
+                gn = sorted({i["p2"] for i in infos}, reverse=True)
+                want = lambda t: [t] if t == 1 else sorted({t - t // 2, t // 2}, reverse=True)
+                assert gm == want(tm) and gn == want(tn), (m, n, blocks)
+                assert len(blocks) == (1 if tm == 1 else 2) * (1 if tn == 1 else 2)

@@ -273,9 +273,9 @@ def test_graph_plan_replays_and_descriptor_updates(ctx):
         iaat.iaat_vbplan_destroy(plan)
 
 
-def test_queue_counters_reset_across_many_calls(ctx):
-    """Each batched launch leaves its counter slot at zero: 260 calls (the
-    256-slot ring wraps) each add A*B once to C (alpha = beta = 1)."""
+def test_repeated_batched_calls_apply_once_each(ctx):
+    """260 back-to-back batched calls each add A*B exactly once to C
+    (alpha = beta = 1): no problem is skipped or computed twice."""
     ps = inputs.uneven_batch(100, seed=93, integer=True)
     ps.alpha[:] = 1.0
     ps.beta[:] = 1.0
