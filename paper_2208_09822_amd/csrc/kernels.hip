@@ -127,7 +127,7 @@ __constant__ int kKidP2[IAAT_NUM_KIDS] = {
 // buffer are left to vbatched_direct_kernel; quick returns and status codes
 // are handled here.
 
-constexpr int kStage = 19456;        // floats of staging per work-group (>= one 80x80x80 problem)
+constexpr int kStage = 19440;        // floats of staging per work-group (>= one 80x80x80 problem)
 constexpr int kMaxBatch = 16;        // problems per batch
 constexpr int kMaxBatchBlocks = 64;  // plan blocks per batch
 constexpr int kWaves = 8;
@@ -154,6 +154,7 @@ __shared__ BatchProb g_bprob[kMaxBatch];
 __shared__ uint32_t g_bblk[kMaxBatchBlocks];  // plan block | problem slot << 24
 __shared__ CopyJob g_copy[3 * kMaxBatch];
 __shared__ int g_bhead[4];                    // problems, blocks, copies, more-to-come
+__shared__ __attribute__((aligned(16))) uint32_t g_ring[2][16 * 16];  // descriptor windows read ahead
 
 // Staged size of one problem: A, B and (beta != 0) C spans, each widened to
 // whole 16-byte units around it.
@@ -192,20 +193,29 @@ __device__ __forceinline__ void run_block_lds(int kid, const LdsProb& P, int i0,
   else LdsKred<TA, TB>::run(P, i0, j0, sync, p1, p2);
 }
 
-// This work-group's share of a span copy: all 512 threads take consecutive
-// 16-byte units (each lane's 16 bytes land at its wavefront's LDS base + 16 *
-// lane).
-__device__ __forceinline__ void stage_span_group(const float* g16, lds_f* dst, int n4) {
+// One 16-byte memory-to-LDS load: this lane's 16 bytes land at `base` + 16 *
+// lane (`base` is the same for the whole wavefront).
+__device__ __forceinline__ void copy16_lds(const float* g16, lds_f* base) {
   typedef __attribute__((address_space(1))) const void gvoid;
   typedef __attribute__((address_space(3))) void lvoid;
-  const int l = lane();
-  for (int t = (int)threadIdx.x; t < n4; t += 64 * kWaves)
-    __builtin_amdgcn_global_load_lds((gvoid*)(g16 + 4 * t), (lvoid*)(dst + 4 * (t - l)), 16, 0, 0);
+  __builtin_amdgcn_global_load_lds((gvoid*)g16, (lvoid*)base, 16, 0, 0);
+}
+
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ float unif(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ const void* unip(const void* p) {
+  const uint64_t v = (uint64_t)p;
+  return (const void*)(((uint64_t)(uint32_t)uni((int)(v >> 32)) << 32) | (uint32_t)uni((int)v));
 }
 
 __device__ __forceinline__ int rdl(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
 __device__ __forceinline__ uint32_t rdl(uint32_t v, int l) {
   return (uint32_t)__builtin_amdgcn_readlane((int)v, l);
+}
+__device__ __forceinline__ float rdlf(float v, int l) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
 }
 
 // kWin descriptors (lane l < kWin holds problem base + l) and plan heads.
@@ -230,6 +240,28 @@ __device__ __forceinline__ void window_load_plan(DescWindow& W, const PlanEntry*
   W.b1 = e->blk[1];
   W.b2 = e->blk[2];
   W.b3 = e->blk[3];
+}
+
+// Window read-ahead through LDS: one memory-to-LDS load brings a window's
+// 16 descriptors (lane L: bytes 16L..16L+15 of the 1 KB); lanes past the
+// end of the array load nothing.
+__device__ __forceinline__ void ring_load(uint32_t* slot, const VbArgs& a, int64_t base) {
+  const int L = lane();
+  if (base + (L >> 2) < a.count)
+    copy16_lds((const float*)(reinterpret_cast<const char*>(a.probs + base) + 16 * L),
+               (lds_f*)(__attribute__((address_space(3))) uint32_t*)slot);
+}
+
+__device__ __forceinline__ void window_from_ring(DescWindow& W, const uint32_t* slot) {
+  const uint4* src = reinterpret_cast<const uint4*>(slot + 16 * (lane() & (kWin - 1)));
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const uint4 v = src[i];
+    W.w[4 * i] = v.x;
+    W.w[4 * i + 1] = v.y;
+    W.w[4 * i + 2] = v.z;
+    W.w[4 * i + 3] = v.w;
+  }
 }
 
 // The problem held by this lane / by lane `l` of a window.
@@ -297,24 +329,28 @@ __device__ __forceinline__ int scan16(int v) {
 // lane) plus prefix sums, then every taken lane writes its own table
 // entries; so the cost per batch does not grow with the number of problems.
 __device__ __forceinline__ void pack_batch(const VbArgs& a, int64_t G, int64_t nwin, int64_t& win,
-                                           int& i, DescWindow& W0, DescWindow& W1, bool& plan1,
+                                           int& i, DescWindow& W0, DescWindow& W1, int& r,
                                            LaneProb& LP) {
   const int l = lane();
   int used = 0, np = 0, nb = 0, nc = 0;
   bool more = true;
   for (;;) {
-    if (i == kWin) {  // window done: advance (the next window was prefetched)
+    if (i == kWin) {  // window done: W1 (words and plan head) was read one window ahead
       win += G;
       if (win >= nwin) {
         more = false;
         break;
       }
-      if (!plan1) window_load_plan(W1, a.table);
       W0 = W1;
-      plan1 = false;
       i = 0;
-      if (win + G < nwin) window_load(W1, a, (win + G) * kWin);
+      ++r;
       LP = classify(W0, l < kWin && win * kWin + l < a.count);
+      if (win + G < nwin) {
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // the ring slot has landed
+        window_from_ring(W1, g_ring[(r + 1) & 1]);
+        window_load_plan(W1, a.table);
+        if (win + 2 * G < nwin) ring_load(g_ring[r & 1], a, (win + 2 * G) * kWin);
+      }
     }
     // candidates: lanes >= i that are staged
     const bool cand = l >= i && l < kWin && LP.cls == CLS_STAGE;
@@ -399,50 +435,60 @@ void vbatched_f32_kernel(VbArgs a) {
   if (win >= nwin) return;
   DescWindow W0, W1;
   LaneProb LP{};
-  bool plan1 = false;
+  int r = 0;  // windows advanced so far
   int i = 0;
   if (w == 0) {
     window_load(W0, a, win * kWin);
     window_load_plan(W0, a.table);
-    if (win + G < nwin) window_load(W1, a, (win + G) * kWin);
+    if (win + G < nwin) {
+      window_load(W1, a, (win + G) * kWin);
+      window_load_plan(W1, a.table);
+    }
+    if (win + 2 * G < nwin) ring_load(g_ring[0], a, (win + 2 * G) * kWin);
     LP = classify(W0, lane() < kWin && win * kWin + lane() < a.count);
   }
   lds_f* stage = (lds_f*)g_stage;
   for (;;) {
-    if (w == 0) pack_batch(a, G, nwin, win, i, W0, W1, plan1, LP);
+    if (w == 0) pack_batch(a, G, nwin, win, i, W0, W1, r, LP);
     __syncthreads();  // batch tables visible
     const int np = __builtin_amdgcn_readfirstlane(g_bhead[0]);
     const int nb = __builtin_amdgcn_readfirstlane(g_bhead[1]);
     const int nc = __builtin_amdgcn_readfirstlane(g_bhead[2]);
     const int more = __builtin_amdgcn_readfirstlane(g_bhead[3]);
     if (np > 0) {
-      // every wavefront issues its share of every copy, then one wait
+      // Copies: job c is cut into 64-unit chunks (one memory-to-LDS load
+      // instruction each); chunks are numbered across jobs and chunk q goes
+      // to wavefront q mod 8.  Lane c holds job c's entry (one LDS read).
+      CopyJob my{};
+      if (lane() < nc) my = g_copy[lane()];
+      const uint64_t src_v = (uint64_t)my.src;
+      int qbase = 0;
       for (int c = 0; c < nc; ++c) {
-        const CopyJob& cj = g_copy[c];
-        const uint64_t sp = (uint64_t)cj.src;
-        const uint64_t su = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(sp >> 32)) << 32) |
-                            (uint32_t)__builtin_amdgcn_readfirstlane((int)sp);
-        stage_span_group((const float*)su, stage + __builtin_amdgcn_readfirstlane(cj.dst),
-                         __builtin_amdgcn_readfirstlane(cj.n4));
+        const int n4 = rdl(my.n4, c);
+        const int nch = (n4 + 63) >> 6;
+        if (n4 > 0) {
+          const uint64_t su = ((uint64_t)rdl((uint32_t)(src_v >> 32), c) << 32) | rdl((uint32_t)src_v, c);
+          const float* g16 = (const float*)su;
+          lds_f* dst = stage + rdl(my.dst, c);
+          for (int ch = (w - qbase) & (kWaves - 1); ch < nch; ch += kWaves) {
+            const int t = 64 * ch + lane();
+            if (t < n4) copy16_lds(g16 + 4 * t, dst + 256 * ch);
+          }
+        }
+        qbase += nch;
       }
       staged_barrier();
-      // blocks w, w + 8, ... of the batch
-      for (int bi = w; bi < nb; bi += kWaves) {
-        const uint32_t e = (uint32_t)__builtin_amdgcn_readfirstlane((int)g_bblk[bi]);
+      // Blocks w, w + 8, ...: lane t holds block w + 8t.
+      const int myb = w + kWaves * lane();
+      const uint32_t e_v = myb < nb ? g_bblk[myb] : 0u;
+      for (int t = 0; w + kWaves * t < nb; ++t) {
+        const uint32_t e = rdl(e_v, t);
         const BatchProb& bp = g_bprob[e >> 24];
-        const int lc = __builtin_amdgcn_readfirstlane(bp.lc);
-        const uint64_t cp = (uint64_t)bp.C;
-        const uint64_t cu = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(cp >> 32)) << 32) |
-                            (uint32_t)__builtin_amdgcn_readfirstlane((int)cp);
-        const LdsProb L{stage + __builtin_amdgcn_readfirstlane(bp.la),
-                        stage + __builtin_amdgcn_readfirstlane(bp.lb), lc >= 0 ? stage + lc : nullptr,
-                        (float*)cu, __builtin_amdgcn_readfirstlane(bp.m),
-                        __builtin_amdgcn_readfirstlane(bp.n), __builtin_amdgcn_readfirstlane(bp.k),
-                        __builtin_amdgcn_readfirstlane(bp.lda), __builtin_amdgcn_readfirstlane(bp.ldb),
-                        __builtin_amdgcn_readfirstlane(bp.ldc),
-                        __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, bp.alpha))),
-                        __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, bp.beta)))};
-        const int trans = __builtin_amdgcn_readfirstlane(bp.trans);
+        const int lc = uni(bp.lc);
+        const LdsProb L{stage + uni(bp.la), stage + uni(bp.lb), lc >= 0 ? stage + lc : nullptr,
+                        (float*)unip(bp.C), uni(bp.m), uni(bp.n), uni(bp.k), uni(bp.lda),
+                        uni(bp.ldb), uni(bp.ldc), unif(bp.alpha), unif(bp.beta)};
+        const int trans = uni(bp.trans);
         const int kid = blk_kid(e), i0 = blk_i0(e), j0 = blk_j0(e);
         switch (trans) {
           case 0: run_block_lds<0, 0>(kid, L, i0, j0, SYNC_NONE); break;
@@ -455,15 +501,6 @@ void vbatched_f32_kernel(VbArgs a) {
     if (!more) break;
     __syncthreads();  // the buffer and the batch tables are refilled next
   }
-}
-
-__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
-__device__ __forceinline__ float unif(float v) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
-}
-__device__ __forceinline__ const void* unip(const void* p) {
-  const uint64_t v = (uint64_t)p;
-  return (const void*)(((uint64_t)(uint32_t)uni((int)(v >> 32)) << 32) | (uint32_t)uni((int)v));
 }
 
 // A problem that does not fit the staging buffer, on one wavefront: every
