@@ -56,9 +56,20 @@ typedef void* iaat_stream_t; /* a hipStream_t; NULL means the null stream */
 enum { IAAT_OP_N = 0, IAAT_OP_T = 1 };
 
 /* Precision of A and B for the batched form (C, alpha, beta and the
- * accumulation are always FP32). */
+ * accumulation are always FP32).  The reduced-precision modes extend the
+ * paper's FP32/FP64 kernels (Table 1) to matrix-core input types; each
+ * product of two such inputs is exact in FP32, so results differ from the
+ * exact product of the dequantised inputs only by FP32 accumulation. */
 enum {
-    IAAT_PREC_F32 = 0 /* A, B float */
+    IAAT_PREC_F32 = 0,    /* A, B float */
+    IAAT_PREC_BF16 = 1,   /* A, B bfloat16 (uint16 codes) */
+    IAAT_PREC_F16 = 2,    /* A, B IEEE binary16 */
+    IAAT_PREC_F8E4M3 = 3, /* A, B FP8 E4M3 (OCP, bias 7, max 448) of x * 2^e per matrix;
+                             ab_scale = 2^-(eA + eB) undoes the scales */
+    IAAT_PREC_BF16X3 = 4  /* A, B each a bfloat16 pair hi = bf16(x), lo = bf16(x - hi):
+                             the lo matrix follows the hi matrix, ld * (stored columns)
+                             elements after it; op(A)op(B) is taken as
+                             lo*hi + hi*lo + hi*hi (split-bfloat16 compensation) */
 };
 
 #define IAAT_OK 0
@@ -129,10 +140,15 @@ typedef struct iaat_problem {
  * `stream`.  The descriptors are already in device
  * memory (`probs_dev`, count entries); validation, tile-plan lookup and the
  * work queue all run on the device, so the host does O(1) work.
- *   count >= 0 (arg 3); prec IAAT_PREC_F32 (arg 4); status: NULL or a device
- *   array of count int32 (arg 5).
- * Problems must not write overlapping C.  Results are bitwise identical to
- * iaat_gemm on each problem (same tile plan, same block kernels).
+ *   count >= 0 (arg 3); prec one of IAAT_PREC_* (arg 4); status: NULL or a
+ *   device array of count int32 (arg 5).
+ * Problems must not write overlapping C.  FP32 results are bitwise identical
+ * to iaat_gemm on each problem (same tile plan, same block kernels).  With
+ * a reduced-precision `prec`, A and B hold codes of that type (ld in
+ * elements) and alpha * ab_scale multiplies op(A)op(B); those problems are
+ * covered by 16 x 16 matrix-core tiles with FP32 accumulation (FP8 codes are
+ * widened exactly to binary16 for the matrix cores, whose FP8 dot product
+ * does not sum in full FP32 precision).
  * Does not allocate; keeps no state on the device between calls. */
 int iaat_gemm_vbatched_device(iaat_ctx_t ctx, const iaat_problem* probs_dev, int64_t count,
                               int prec, int32_t* status, iaat_stream_t stream);
@@ -145,6 +161,34 @@ int iaat_gemm_vbatched_device(iaat_ctx_t ctx, const iaat_problem* probs_dev, int
  * its capacity. */
 int iaat_gemm_vbatched(iaat_ctx_t ctx, const iaat_problem* probs_host, int64_t count,
                        int prec, int32_t* status, iaat_stream_t stream);
+
+/* One quantisation job: the A and B operands of one problem.  Each source is
+ * a contiguous FP32 array of *_n elements (a whole stored matrix, ld times
+ * stored columns); the destination receives *_n codes of the target type
+ * (2 * *_n bfloat16 for IAAT_PREC_BF16X3: hi then lo).  All pointers are
+ * device memory; a_n or b_n may be 0 (nothing done for that operand). */
+typedef struct iaat_qjob {
+    const float* a_src;
+    const float* b_src;
+    void* a_dst;
+    void* b_dst;
+    int64_t a_n, b_n;
+    iaat_problem* prob; /* NULL, or a device descriptor whose ab_scale is set:
+                           2^-(eA + eB) for FP8, 1 otherwise */
+    float* scales;      /* NULL, or device float[2] receiving 2^eA, 2^eB (FP8; 1 otherwise) */
+} iaat_qjob;
+
+/* Quantises the operands of `count` problems (jobs_dev: device array) to
+ * `prec` in one launch on `stream`, rounding to nearest even:
+ *   BF16, F16   direct rounding of x (binary16 overflows to inf past 65504);
+ *   F8E4M3      per matrix, e = the largest integer with absmax * 2^e <= 448
+ *               (0 for an all-zero or non-finite absmax), codes of x * 2^e
+ *               saturating at +-448, zero always encoded +0;
+ *   BF16X3      hi = bf16(x), lo = bf16(x - hi) (x - hi is exact in FP32).
+ * Errors: -1 ctx, -2 prec (not a reduced-precision mode), -3 jobs_dev NULL
+ * with count > 0, -4 count < 0. */
+int iaat_quantize_batch(iaat_ctx_t ctx, int prec, const iaat_qjob* jobs_dev, int64_t count,
+                        iaat_stream_t stream);
 
 /* Graph-replayed batch: captures the batched launch for the descriptor
  * array `probs_dev` (count entries) into a HIP graph once; each

@@ -209,20 +209,46 @@ int iaat_gemm(iaat_ctx_t ctx, int ta, int tb, int64_t m, int64_t n, int64_t k, f
   return e == hipSuccess ? IAAT_OK : hip_fail(e, "iaat_gemm: launch");
 }
 
+// The batched launch(es) for one descriptor array: the staged FP32 kernel
+// and its companion, or the reduced-precision kernel.
+static hipError_t launch_batch(iaat_ctx_t ctx, const iaat_problem* probs_dev, int64_t count, int prec,
+                               int32_t* status, hipStream_t s) {
+  VbArgs a{probs_dev, count, status, ctx->table_dev};
+  if (prec != IAAT_PREC_F32) {
+    const int64_t cap = 8LL * ctx->num_cu;  // work-groups of 256 threads, grid-stride over problems
+    return launch_vbatched_lowp(a, prec, (int)(count < cap ? count : cap), s);
+  }
+  const int grid = (int)(count < ctx->vb_grid ? count : ctx->vb_grid);
+  const int dgrid = (int)((count + 63) / 64);  // one screening wavefront per 64 problems
+  return launch_vbatched_f32(a, grid, dgrid, s);
+}
+
+int iaat_quantize_batch(iaat_ctx_t ctx, int prec, const iaat_qjob* jobs_dev, int64_t count,
+                        iaat_stream_t stream) {
+  if (!ctx) return fail(-1, "iaat_quantize_batch: ctx is NULL");
+  if (prec < IAAT_PREC_BF16 || prec > IAAT_PREC_BF16X3)
+    return fail(-2, "iaat_quantize_batch: prec=%d is not a reduced-precision mode", prec);
+  if (count < 0) return fail(-4, "iaat_quantize_batch: count=%lld", (long long)count);
+  if (count > 0 && !jobs_dev) return fail(-3, "iaat_quantize_batch: jobs is NULL");
+  if (count == 0) return IAAT_OK;
+  DeviceGuard g(ctx->device);
+  const int64_t cap = 8LL * ctx->num_cu;
+  const hipError_t e = launch_quantize(prec, jobs_dev, count, (int)(count < cap ? count : cap),
+                                       (hipStream_t)stream);
+  return e == hipSuccess ? IAAT_OK : hip_fail(e, "iaat_quantize_batch: launch");
+}
+
 int iaat_gemm_vbatched_device(iaat_ctx_t ctx, const iaat_problem* probs_dev, int64_t count,
                               int prec, int32_t* status, iaat_stream_t stream) {
   if (!ctx) return fail(-1, "iaat_gemm_vbatched_device: ctx is NULL");
   if (count < 0 || count > 0x7fffffffLL)
     return fail(-3, "iaat_gemm_vbatched_device: count=%lld", (long long)count);
   if (count > 0 && !probs_dev) return fail(-2, "iaat_gemm_vbatched_device: probs is NULL");
-  if (prec != IAAT_PREC_F32) return fail(-4, "iaat_gemm_vbatched_device: prec=%d", prec);
+  if (prec < IAAT_PREC_F32 || prec > IAAT_PREC_BF16X3) return fail(-4, "iaat_gemm_vbatched_device: prec=%d", prec);
   if (count == 0) return IAAT_OK;
   DeviceGuard g(ctx->device);
   hipStream_t s = (hipStream_t)stream;
-  VbArgs a{probs_dev, count, status, ctx->table_dev};
-  const int grid = (int)(count < ctx->vb_grid ? count : ctx->vb_grid);
-  const int dgrid = (int)((count + 63) / 64);  // one screening wavefront per 64 problems
-  const hipError_t e = launch_vbatched_f32(a, grid, dgrid, s);
+  const hipError_t e = launch_batch(ctx, probs_dev, count, prec, status, s);
   return e == hipSuccess ? IAAT_OK : hip_fail(e, "iaat_gemm_vbatched_device: launch");
 }
 
@@ -232,7 +258,7 @@ int iaat_vbplan_create(iaat_ctx_t ctx, const iaat_problem* probs_dev, int64_t co
   if (count < 0 || count > 0x7fffffffLL)
     return fail(-3, "iaat_vbplan_create: count=%lld", (long long)count);
   if (count > 0 && !probs_dev) return fail(-2, "iaat_vbplan_create: probs is NULL");
-  if (prec != IAAT_PREC_F32) return fail(-4, "iaat_vbplan_create: prec=%d", prec);
+  if (prec < IAAT_PREC_F32 || prec > IAAT_PREC_BF16X3) return fail(-4, "iaat_vbplan_create: prec=%d", prec);
   if (!out) return fail(-6, "iaat_vbplan_create: out is NULL");
   *out = nullptr;
   DeviceGuard g(ctx->device);
@@ -252,10 +278,7 @@ int iaat_vbplan_create(iaat_ctx_t ctx, const iaat_problem* probs_dev, int64_t co
       (e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal)) != hipSuccess)
     return cleanup(hip_fail(e, "iaat_vbplan_create: capture setup"));
   if (count > 0) {
-    VbArgs a{probs_dev, count, status, ctx->table_dev};
-    const int grid = (int)(count < ctx->vb_grid ? count : ctx->vb_grid);
-    const int dgrid = (int)((count + 63) / 64);
-    e = launch_vbatched_f32(a, grid, dgrid, cs);
+    e = launch_batch(ctx, probs_dev, count, prec, status, cs);
     if (e != hipSuccess) {
       hipGraph_t tmp = nullptr;
       (void)hipStreamEndCapture(cs, &tmp);
@@ -294,7 +317,7 @@ int iaat_gemm_vbatched(iaat_ctx_t ctx, const iaat_problem* probs_host, int64_t c
   if (count < 0 || count > 0x7fffffffLL)
     return fail(-3, "iaat_gemm_vbatched: count=%lld", (long long)count);
   if (count > 0 && !probs_host) return fail(-2, "iaat_gemm_vbatched: probs is NULL");
-  if (prec != IAAT_PREC_F32) return fail(-4, "iaat_gemm_vbatched: prec=%d", prec);
+  if (prec < IAAT_PREC_F32 || prec > IAAT_PREC_BF16X3) return fail(-4, "iaat_gemm_vbatched: prec=%d", prec);
   if (count == 0) return IAAT_OK;
   DeviceGuard g(ctx->device);
   std::lock_guard<std::mutex> lk(ctx->stage_mu);

@@ -27,7 +27,8 @@ except Exception:  # pragma: no cover
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libiaat.so")
 
 IAAT_OP_N, IAAT_OP_T = 0, 1
-IAAT_PREC_F32 = 0
+IAAT_PREC_F32, IAAT_PREC_BF16, IAAT_PREC_F16, IAAT_PREC_F8E4M3, IAAT_PREC_BF16X3 = 0, 1, 2, 3, 4
+PREC_NAMES = {0: "f32", 1: "bf16", 2: "f16", 3: "f8e4m3", 4: "bf16x3"}
 IAAT_OK = 0
 IAAT_ERR_HIP = -100
 IAAT_ERR_NOMEM = -101
@@ -44,6 +45,14 @@ PROBLEM_DTYPE = np.dtype([
     ("alpha", "<f4"), ("beta", "<f4"), ("ab_scale", "<f4"),
 ])
 assert PROBLEM_DTYPE.itemsize == 64
+
+
+# iaat_qjob, 64 bytes
+QJOB_DTYPE = np.dtype([
+    ("a_src", "<u8"), ("b_src", "<u8"), ("a_dst", "<u8"), ("b_dst", "<u8"),
+    ("a_n", "<i8"), ("b_n", "<i8"), ("prob", "<u8"), ("scales", "<u8"),
+])
+assert QJOB_DTYPE.itemsize == 64
 
 
 class IaatBlock(ctypes.Structure):
@@ -80,6 +89,7 @@ def lib():
                 "iaat_gemm_vbatched_device": (i32, [vp, vp, i64, i32, vp, vp]),
                 "iaat_gemm_vbatched": (i32, [vp, vp, i64, i32, vp, vp]),
                 "iaat_vbplan_create": (i32, [vp, vp, i64, i32, vp, ctypes.POINTER(vp)]),
+                "iaat_quantize_batch": (i32, [vp, i32, vp, i64, vp]),
                 "iaat_vbplan_launch": (i32, [vp, vp]),
                 "iaat_vbplan_destroy": (i32, [vp]),
                 "iaat_plan_query": (i32, [vp, i32, i32, i32, ctypes.POINTER(IaatBlock), i32]),
@@ -135,6 +145,10 @@ def iaat_gemm_vbatched(ctx, probs_host: np.ndarray, count=None, prec=IAAT_PREC_F
     count = len(arr) if count is None else int(count)
     _check(lib().iaat_gemm_vbatched(ctx, arr.ctypes.data if count else None, count, int(prec),
                                     status or None, stream or None))
+
+
+def iaat_quantize_batch(ctx, prec, jobs_dev, count, stream=0) -> None:
+    _check(lib().iaat_quantize_batch(ctx, prec, jobs_dev or None, count, stream or None))
 
 
 def iaat_vbplan_create(ctx, probs_dev, count, prec=IAAT_PREC_F32, status=0) -> int:
@@ -202,6 +216,35 @@ def descriptors(ps, base_ptr: int, elem_bytes: int = 4, ab_scale=None) -> np.nda
     d["alpha"], d["beta"] = ps.alpha, ps.beta
     d["ab_scale"] = 1.0 if ab_scale is None else ab_scale
     return d
+
+
+PREC_ELEM_BYTES = {IAAT_PREC_BF16: 2, IAAT_PREC_F16: 2, IAAT_PREC_F8E4M3: 1, IAAT_PREC_BF16X3: 2}
+# elements of destination per source element (a hi/lo pair for BF16X3)
+PREC_SPAN = {IAAT_PREC_BF16: 1, IAAT_PREC_F16: 1, IAAT_PREC_F8E4M3: 1, IAAT_PREC_BF16X3: 2}
+
+
+def lowp_layout(ps, prec, src_base: int, dst_base: int, desc_dev: int):
+    """Quantisation jobs and reduced-precision descriptors for a ProblemSet
+    whose FP32 buffer is at ``src_base``; codes go to a device buffer at
+    ``dst_base`` holding ``PREC_SPAN[prec] * len(ps.buf)`` elements of
+    ``PREC_ELEM_BYTES[prec]`` bytes, each operand at its FP32 element offset
+    times the span.  ``desc_dev`` is where the descriptor array will live (the
+    jobs point at its ab_scale fields).  Returns (jobs, descriptors)."""
+    eb, sp = PREC_ELEM_BYTES[prec], PREC_SPAN[prec]
+    jobs = np.zeros(ps.count, dtype=QJOB_DTYPE)
+    lda, ldb = ps.lda.astype(np.int64), ps.ldb.astype(np.int64)
+    ta, tb = (ps.trans & 1).astype(bool), (ps.trans & 2).astype(bool)
+    cols_a = np.where(ta, ps.m, ps.k).astype(np.int64)
+    cols_b = np.where(tb, ps.k, ps.n).astype(np.int64)
+    jobs["a_src"] = src_base + ps.a_off.astype(np.uint64) * 4
+    jobs["b_src"] = src_base + ps.b_off.astype(np.uint64) * 4
+    jobs["a_dst"] = dst_base + ps.a_off.astype(np.uint64) * (eb * sp)
+    jobs["b_dst"] = dst_base + ps.b_off.astype(np.uint64) * (eb * sp)
+    jobs["a_n"], jobs["b_n"] = lda * cols_a, ldb * cols_b
+    jobs["prob"] = desc_dev + np.arange(ps.count, dtype=np.uint64) * PROBLEM_DTYPE.itemsize
+    d = descriptors(ps, src_base)
+    d["A"], d["B"] = jobs["a_dst"], jobs["b_dst"]
+    return jobs, d
 
 
 class Context:

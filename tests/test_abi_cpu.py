@@ -97,3 +97,11 @@ def test_default_matrix_core_plans_use_at_most_four_balanced_blocks():
                 want = lambda t: [t] if t == 1 else sorted({t - t // 2, t // 2}, reverse=True)
                 assert gm == want(tm) and gn == want(tn), (m, n, blocks)
                 assert len(blocks) == (1 if tm == 1 else 2) * (1 if tn == 1 else 2)
+
+
+def test_quantize_and_precision_arguments_rejected_before_device_work():
+    lib = iaat.lib()
+    assert lib.iaat_quantize_batch(None, iaat.IAAT_PREC_BF16, None, 1, None) == -1
+    assert lib.iaat_gemm_vbatched_device(None, None, 1, iaat.IAAT_PREC_F8E4M3, None, None) == -1
+    assert iaat.QJOB_DTYPE.itemsize == 64 and iaat.PROBLEM_DTYPE.itemsize == 64
+    assert set(iaat.PREC_NAMES) == {0, 1, 2, 3, 4}
