@@ -203,6 +203,99 @@ int iaat_vbplan_create(iaat_ctx_t ctx, const iaat_problem* probs_dev, int64_t co
 int iaat_vbplan_launch(iaat_vbplan_t plan, iaat_stream_t stream);
 int iaat_vbplan_destroy(iaat_vbplan_t plan); /* NULL accepted */
 
+/* ---------------------------------------------------------------- serving */
+
+/* A request loop over the batched form (continuous batching).  Requests
+ * arrive at any time with a list of GEMMs whose A and B stay resident in
+ * device memory; a scheduler thread admits them in arrival order while their
+ * outputs fit in a server-owned device arena of `mem_cap_bytes` (admission
+ * by memory), packs admitted requests into batched launches of at most
+ * `max_batch_gemms` problems, and keeps up to two launches in flight on each
+ * of `n_streams` streams, so requests that arrive while others run join the
+ * next launch as soon as a launch slot and arena space free up.  Each GEMM's
+ * result is exactly what the batched form computes for it alone (the tile
+ * plan depends only on the problem, and the block kernels do not depend on
+ * the batch). */
+typedef struct iaat_server* iaat_server_t;
+
+typedef struct iaat_serve_cfg {
+    uint64_t mem_cap_bytes; /* output arena (admission cap), > 0 */
+    int32_t n_streams;      /* 1..16 */
+    int32_t max_batch_gemms;/* problems per launch, >= 1; also the largest request */
+    int32_t prec;           /* IAAT_PREC_* of every served GEMM */
+    int32_t reserved;
+} iaat_serve_cfg;
+
+enum { IAAT_REQ_QUEUED = 0, IAAT_REQ_ADMITTED = 1, IAAT_REQ_DONE = 3 };
+
+typedef struct iaat_req_status {
+    int32_t state;      /* IAAT_REQ_* */
+    int32_t err;        /* 0, or the first non-zero per-problem status code */
+    double t_arrival;   /* seconds on the server clock (iaat_serve_clock) */
+    double t_launch;    /* admitted and launched */
+    double t_done;      /* completion observed */
+    float* out;         /* device address of the request's outputs while kept
+                           (see iaat_serve_submit), else NULL */
+} iaat_req_status;
+
+typedef struct iaat_serve_stats {
+    uint64_t submitted, done, failed, launches, gemms_done;
+    double p50, p99, max_latency; /* seconds, t_done - t_arrival of done requests */
+    double gflops;                /* 2MNK of done requests / (last t_done - first t_arrival) */
+    uint64_t peak_admitted_bytes; /* most arena bytes held at once */
+    int64_t peak_queue_depth;     /* most requests waiting for admission */
+} iaat_serve_stats;
+
+/* Starts a server on the context's device (allocates the arena, streams,
+ * pinned staging; starts the scheduler thread).
+ * Errors: -1 ctx; -2 cfg NULL or out of range; -3 out NULL; IAAT_ERR_NOMEM;
+ * IAAT_ERR_HIP. */
+int iaat_serve_start(iaat_ctx_t ctx, const iaat_serve_cfg* cfg, iaat_server_t* out);
+
+/* Submits one request of `count` GEMMs (host descriptors, copied by the
+ * call).  For each GEMM, A and B are device operands and C names the
+ * INITIAL value C0 (device, ldc x n, read only when beta != 0; NULL allowed
+ * when beta == 0): the result is written to the request's own output region
+ * in the arena, GEMM i at float offset out_off(i) = sum over earlier GEMMs
+ * of ldc*n rounded up to 64 floats.  `t_arrival` is the request's arrival on
+ * the server clock (< 0: now); latencies are measured from it.  With
+ * keep_output != 0 the output region stays allocated after completion until
+ * iaat_serve_release; otherwise it is freed at completion.
+ * Errors: -1 server; -2 gemms NULL or count < 1; -3 count > max_batch_gemms,
+ * or the outputs exceed the arena; -4 a GEMM's arguments are invalid (its
+ * number in iaat_last_error); -6 ticket NULL; IAAT_ERR_UNSUPPORTED after stop. */
+int iaat_serve_submit(iaat_server_t srv, const iaat_problem* gemms_host, int64_t count,
+                      double t_arrival, int keep_output, uint64_t* ticket);
+
+/* Status of a request: returns 0 when done, 1 while queued or running, or
+ * -2 for an unknown ticket; fills *st when st is not NULL. */
+int iaat_serve_poll(iaat_server_t srv, uint64_t ticket, iaat_req_status* st);
+
+/* Frees a kept output region (the request must be done). -2 unknown ticket
+ * or not kept, -3 not done. */
+int iaat_serve_release(iaat_server_t srv, uint64_t ticket);
+
+/* Seconds since the server started (the clock of t_arrival / t_done). */
+double iaat_serve_clock(iaat_server_t srv);
+
+int iaat_serve_stats_get(iaat_server_t srv, iaat_serve_stats* out);
+
+/* Open-loop replay of a request trace (a load generator running in a native
+ * thread): request r arrives t_arrival[r] seconds after the call starts and
+ * holds n_gemms[r] GEMMs, the pool entries pool_idx[first_r ..] (first_r =
+ * sum of earlier n_gemms) of the host descriptor array `pool` (pool_size
+ * entries, C = initial values).  Each request is submitted at its arrival
+ * time (or at once when the replay is behind), then the call waits for all
+ * of them; latency_out (NULL or n_req doubles) receives t_done - t_arrival
+ * per request.  Returns 0, or the first submit error. */
+int iaat_serve_replay(iaat_server_t srv, int64_t n_req, const double* t_arrival,
+                      const int32_t* n_gemms, const int64_t* pool_idx, const iaat_problem* pool,
+                      int64_t pool_size, double* latency_out);
+
+/* Waits for every submitted request, stops the scheduler and frees the
+ * server.  NULL accepted. */
+int iaat_serve_stop(iaat_server_t srv);
+
 /* ------------------------------------------------------ introspection */
 
 /* One block of a tile plan: rows [i0, i0+rows) x cols [j0, j0+cols) of a

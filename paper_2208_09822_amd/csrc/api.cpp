@@ -15,34 +15,15 @@
 #include "iaat_internal.h"
 #include "kernels.h"
 #include "tiler.h"
+#include "api_internal.h"
 
 using namespace iaat;
 
-struct iaat_vbplan {
-  iaat_ctx* ctx = nullptr;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-  int64_t count = 0;
-};
-
-struct iaat_ctx {
-  int device = 0;
-  int num_cu = 0;
-  int vb_grid = 0;      // staged batched kernel: work-groups resident at once
-  int direct_grid = 0;  // direct batched kernel: wavefronts resident at once
-  std::vector<PlanEntry> table;
-  PlanEntry* table_dev = nullptr;
-  // staging for descriptors handed over in host memory
-  std::mutex stage_mu;
-  iaat_problem* stage_host = nullptr;
-  iaat_problem* stage_dev = nullptr;
-  int64_t stage_cap = 0;
-  hipEvent_t stage_evt = nullptr;
-};
-
 namespace {
-
 thread_local std::string g_err;
+}  // namespace
+
+namespace iaat {
 
 int fail(int code, const char* fmt, ...) {
   char buf[512];
@@ -58,17 +39,9 @@ int hip_fail(hipError_t e, const char* what) {
   return fail(IAAT_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
 }
 
-struct DeviceGuard {
-  int prev = -1;
-  explicit DeviceGuard(int dev) {
-    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-    if (prev != dev) (void)hipSetDevice(dev);
-  }
-  ~DeviceGuard() {
-    int cur = -1;
-    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
-  }
-};
+}  // namespace iaat
+
+namespace {
 
 const char* arg_name(int st) {
   switch (st) {
@@ -101,6 +74,24 @@ void free_ctx(iaat_ctx* c) {
 }
 
 }  // namespace
+
+namespace iaat {
+
+// The batched launch(es) for one descriptor array: the staged FP32 kernel
+// and its companion, or the reduced-precision kernel.
+hipError_t launch_batch(iaat_ctx_t ctx, const iaat_problem* probs_dev, int64_t count, int prec,
+                        int32_t* status, hipStream_t s) {
+  VbArgs a{probs_dev, count, status, ctx->table_dev};
+  if (prec != IAAT_PREC_F32) {
+    const int64_t cap = 8LL * ctx->num_cu;  // work-groups of 256 threads, grid-stride over problems
+    return launch_vbatched_lowp(a, prec, (int)(count < cap ? count : cap), s);
+  }
+  const int grid = (int)(count < ctx->vb_grid ? count : ctx->vb_grid);
+  const int dgrid = (int)((count + 63) / 64);  // one screening wavefront per 64 problems
+  return launch_vbatched_f32(a, grid, dgrid, s);
+}
+
+}  // namespace iaat
 
 extern "C" {
 
@@ -207,20 +198,6 @@ int iaat_gemm(iaat_ctx_t ctx, int ta, int tb, int64_t m, int64_t n, int64_t k, f
   dev::Prob P{A, B, C, (int)m, (int)n, (int)k, (int)lda, (int)ldb, (int)ldc, alpha, beta};
   e = launch_gemm_f32(P, layout, ctx->table_dev, (int)nsm, (int)nsn, maxb, s);
   return e == hipSuccess ? IAAT_OK : hip_fail(e, "iaat_gemm: launch");
-}
-
-// The batched launch(es) for one descriptor array: the staged FP32 kernel
-// and its companion, or the reduced-precision kernel.
-static hipError_t launch_batch(iaat_ctx_t ctx, const iaat_problem* probs_dev, int64_t count, int prec,
-                               int32_t* status, hipStream_t s) {
-  VbArgs a{probs_dev, count, status, ctx->table_dev};
-  if (prec != IAAT_PREC_F32) {
-    const int64_t cap = 8LL * ctx->num_cu;  // work-groups of 256 threads, grid-stride over problems
-    return launch_vbatched_lowp(a, prec, (int)(count < cap ? count : cap), s);
-  }
-  const int grid = (int)(count < ctx->vb_grid ? count : ctx->vb_grid);
-  const int dgrid = (int)((count + 63) / 64);  // one screening wavefront per 64 problems
-  return launch_vbatched_f32(a, grid, dgrid, s);
 }
 
 int iaat_quantize_batch(iaat_ctx_t ctx, int prec, const iaat_qjob* jobs_dev, int64_t count,

@@ -34,6 +34,14 @@ hipError_t launch_scale_f32(float* C, int m, int n, int ldc, float beta, hipStre
 hipError_t launch_vbatched_f32(const VbArgs& a, int grid, int direct_grid, hipStream_t stream);
 hipError_t vbatched_occupancy(int* blocks_per_cu, int* direct_per_cu);
 
+// Copies float spans (src, dst, n floats), one work-group per span.
+struct CopySpan {
+  const float* src;
+  float* dst;
+  int64_t n;
+};
+hipError_t launch_copy_spans(const CopySpan* spans, int64_t count, int grid, hipStream_t stream);
+
 // Reduced-precision inputs (precision.hip).
 hipError_t launch_quantize(int prec, const iaat_qjob* jobs, int64_t count, int grid, hipStream_t stream);
 hipError_t launch_vbatched_lowp(const VbArgs& a, int prec, int grid, hipStream_t stream);

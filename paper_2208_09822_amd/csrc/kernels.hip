@@ -572,9 +572,21 @@ __global__ __launch_bounds__(64) void vbatched_direct_kernel(VbArgs a) {
   }
 }
 
+__global__ __launch_bounds__(256) void copy_spans_kernel(const CopySpan* spans, int64_t count) {
+  for (int64_t j = blockIdx.x; j < count; j += gridDim.x) {
+    const CopySpan S = spans[j];
+    for (int64_t i = threadIdx.x; i < S.n; i += blockDim.x) S.dst[i] = S.src[i];
+  }
+}
+
 }  // namespace dev
 
 // ------------------------------------------------------------ host launchers
+
+hipError_t launch_copy_spans(const CopySpan* spans, int64_t count, int grid, hipStream_t stream) {
+  hipLaunchKernelGGL(dev::copy_spans_kernel, dim3((unsigned)grid), dim3(256), 0, stream, spans, count);
+  return hipGetLastError();
+}
 
 hipError_t launch_gemm_f32(const dev::Prob& P, int layout, const PlanEntry* table_dev, int nsm,
                            int nsn, int max_blocks, hipStream_t stream) {

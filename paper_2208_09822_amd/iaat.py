@@ -55,6 +55,28 @@ QJOB_DTYPE = np.dtype([
 assert QJOB_DTYPE.itemsize == 64
 
 
+class ServeCfg(ctypes.Structure):
+    _fields_ = [("mem_cap_bytes", ctypes.c_uint64), ("n_streams", ctypes.c_int32),
+                ("max_batch_gemms", ctypes.c_int32), ("prec", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class ReqStatus(ctypes.Structure):
+    _fields_ = [("state", ctypes.c_int32), ("err", ctypes.c_int32), ("t_arrival", ctypes.c_double),
+                ("t_launch", ctypes.c_double), ("t_done", ctypes.c_double), ("out", ctypes.c_void_p)]
+
+
+class ServeStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("done", ctypes.c_uint64), ("failed", ctypes.c_uint64),
+                ("launches", ctypes.c_uint64), ("gemms_done", ctypes.c_uint64),
+                ("p50", ctypes.c_double), ("p99", ctypes.c_double), ("max_latency", ctypes.c_double),
+                ("gflops", ctypes.c_double), ("peak_admitted_bytes", ctypes.c_uint64),
+                ("peak_queue_depth", ctypes.c_int64)]
+
+
+IAAT_REQ_QUEUED, IAAT_REQ_ADMITTED, IAAT_REQ_DONE = 0, 1, 3
+
+
 class IaatBlock(ctypes.Structure):
     _fields_ = [("i0", ctypes.c_int32), ("j0", ctypes.c_int32), ("rows", ctypes.c_int32),
                 ("cols", ctypes.c_int32), ("kid", ctypes.c_int32)]
@@ -90,6 +112,15 @@ def lib():
                 "iaat_gemm_vbatched": (i32, [vp, vp, i64, i32, vp, vp]),
                 "iaat_vbplan_create": (i32, [vp, vp, i64, i32, vp, ctypes.POINTER(vp)]),
                 "iaat_quantize_batch": (i32, [vp, i32, vp, i64, vp]),
+                "iaat_serve_start": (i32, [vp, ctypes.POINTER(ServeCfg), ctypes.POINTER(vp)]),
+                "iaat_serve_submit": (i32, [vp, vp, i64, ctypes.c_double, i32,
+                                            ctypes.POINTER(ctypes.c_uint64)]),
+                "iaat_serve_poll": (i32, [vp, ctypes.c_uint64, ctypes.POINTER(ReqStatus)]),
+                "iaat_serve_release": (i32, [vp, ctypes.c_uint64]),
+                "iaat_serve_clock": (ctypes.c_double, [vp]),
+                "iaat_serve_stats_get": (i32, [vp, ctypes.POINTER(ServeStats)]),
+                "iaat_serve_replay": (i32, [vp, i64, vp, vp, vp, vp, i64, vp]),
+                "iaat_serve_stop": (i32, [vp]),
                 "iaat_vbplan_launch": (i32, [vp, vp]),
                 "iaat_vbplan_destroy": (i32, [vp]),
                 "iaat_plan_query": (i32, [vp, i32, i32, i32, ctypes.POINTER(IaatBlock), i32]),
@@ -149,6 +180,70 @@ def iaat_gemm_vbatched(ctx, probs_host: np.ndarray, count=None, prec=IAAT_PREC_F
 
 def iaat_quantize_batch(ctx, prec, jobs_dev, count, stream=0) -> None:
     _check(lib().iaat_quantize_batch(ctx, prec, jobs_dev or None, count, stream or None))
+
+
+def iaat_serve_start(ctx, mem_cap_bytes, n_streams=4, max_batch_gemms=8192,
+                     prec=IAAT_PREC_F32) -> int:
+    cfg = ServeCfg(mem_cap_bytes, n_streams, max_batch_gemms, prec, 0)
+    h = ctypes.c_void_p()
+    _check(lib().iaat_serve_start(ctx, ctypes.byref(cfg), ctypes.byref(h)))
+    return h.value
+
+
+def iaat_serve_submit(srv, gemms: np.ndarray, t_arrival=-1.0, keep_output=False) -> int:
+    g = np.ascontiguousarray(gemms, dtype=PROBLEM_DTYPE)
+    t = ctypes.c_uint64()
+    _check(lib().iaat_serve_submit(srv, g.ctypes.data, g.shape[0], float(t_arrival),
+                                   int(bool(keep_output)), ctypes.byref(t)))
+    return t.value
+
+
+def iaat_serve_poll(srv, ticket):
+    """(done: bool, ReqStatus)."""
+    st = ReqStatus()
+    rc = lib().iaat_serve_poll(srv, ticket, ctypes.byref(st))
+    if rc < 0:
+        raise IaatError(rc, iaat_last_error())
+    return rc == 0, st
+
+
+def iaat_serve_release(srv, ticket) -> None:
+    _check(lib().iaat_serve_release(srv, ticket))
+
+
+def iaat_serve_clock(srv) -> float:
+    return lib().iaat_serve_clock(srv)
+
+
+def iaat_serve_stats_get(srv) -> dict:
+    st = ServeStats()
+    _check(lib().iaat_serve_stats_get(srv, ctypes.byref(st)))
+    return {name: getattr(st, name) for name, _ in ServeStats._fields_}
+
+
+def iaat_serve_replay(srv, t_arrival, n_gemms, pool_idx, pool: np.ndarray):
+    """Replays an open-loop trace; returns per-request latencies (seconds)."""
+    t = np.ascontiguousarray(t_arrival, dtype=np.float64)
+    n = np.ascontiguousarray(n_gemms, dtype=np.int32)
+    idx = np.ascontiguousarray(pool_idx, dtype=np.int64)
+    p = np.ascontiguousarray(pool, dtype=PROBLEM_DTYPE)
+    lat = np.zeros(t.shape[0], dtype=np.float64)
+    _check(lib().iaat_serve_replay(srv, t.shape[0], t.ctypes.data, n.ctypes.data, idx.ctypes.data,
+                                   p.ctypes.data, p.shape[0], lat.ctypes.data))
+    return lat
+
+
+def iaat_serve_stop(srv) -> None:
+    _check(lib().iaat_serve_stop(srv))
+
+
+def out_offsets(gemms: np.ndarray) -> np.ndarray:
+    """Float offset of each GEMM's output inside a served request's output
+    region (ldc * n rounded up to 64 floats, in order)."""
+    g = np.asarray(gemms, dtype=PROBLEM_DTYPE)
+    f = np.where((g["m"] > 0) & (g["n"] > 0), g["ldc"].astype(np.int64) * g["n"], 0)
+    f = (f + 63) // 64 * 64
+    return np.concatenate([[0], np.cumsum(f)[:-1]]).astype(np.int64)
 
 
 def iaat_vbplan_create(ctx, probs_dev, count, prec=IAAT_PREC_F32, status=0) -> int:

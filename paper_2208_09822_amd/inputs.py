@@ -279,3 +279,14 @@ def pool_indices(total: int, pool_size: int, seed: int):
     """Which pool entries a stream of ``total`` GEMMs refers to (uniform)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     return rng.integers(0, pool_size, total)
+
+
+def serve_pool(size: int = 4096, seed: int = SEED_BASE + 4) -> ProblemSet:
+    """Resident GEMM pool of the serving workload: shapes uniform over the
+    sweep grid (layouts NN/NT/TN/TT, TN limited to its domain), entries
+    U[-1,1], alpha = beta = 1."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    grid = sweep_shapes()
+    pick = rng.integers(0, len(grid), size)
+    return uniform_problems([grid[int(i)] for i in pick], seed=seed + 1000, alpha=1.0, beta=1.0,
+                            name="serve_pool")

@@ -2,6 +2,7 @@
 exports every entry point the public header declares, rejects bad arguments
 before touching a device, and its run-time tiler's built-in plans are valid
 (exact cover, kernel membership) for every (layout, m, n) <= 80."""
+import ctypes
 import os
 import re
 import subprocess
@@ -105,3 +106,14 @@ def test_quantize_and_precision_arguments_rejected_before_device_work():
     assert lib.iaat_gemm_vbatched_device(None, None, 1, iaat.IAAT_PREC_F8E4M3, None, None) == -1
     assert iaat.QJOB_DTYPE.itemsize == 64 and iaat.PROBLEM_DTYPE.itemsize == 64
     assert set(iaat.PREC_NAMES) == {0, 1, 2, 3, 4}
+
+
+def test_serve_arguments_rejected_before_device_work():
+    lib = iaat.lib()
+    h = ctypes.c_void_p()
+    cfg = iaat.ServeCfg(1 << 20, 1, 8, 0, 0)
+    assert lib.iaat_serve_start(None, ctypes.byref(cfg), ctypes.byref(h)) == -1
+    assert lib.iaat_serve_submit(None, None, 1, -1.0, 0, None) == -1
+    assert lib.iaat_serve_poll(None, 1, None) == -1
+    assert lib.iaat_serve_stop(None) == 0
+    assert ctypes.sizeof(iaat.ServeCfg) == 24 and ctypes.sizeof(iaat.ReqStatus) == 40
