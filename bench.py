@@ -63,6 +63,113 @@ def stored_traffic(workload: str):
     return d.get("hbm_bytes_per_launch")
 
 
+def _events_ms(torch, stream, fn, reps):
+    fn()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(reps):
+        fn()
+    b.record(stream)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def plain_nn16(iaat, inputs, h, dev, stream):
+    """1,000 NN problems of 16 x 16 x 16 (alpha 1.5, beta 0.5): one iaat_gemm
+    launch per problem, and the same problems as one batched launch."""
+    import numpy as np
+    import torch
+    ps = inputs.plain_nn16()
+    buf = torch.from_numpy(ps.buf).to(dev)
+    base, sp, L = buf.data_ptr(), stream.cuda_stream, iaat.lib()
+    ao = (base + 4 * ps.a_off).tolist(); bo = (base + 4 * ps.b_off).tolist()
+    co = (base + 4 * ps.c_off).tolist()
+
+    def calls():
+        for q in range(ps.count):
+            L.iaat_gemm(h, 0, 0, 16, 16, 16, 1.5, ao[q], 16, bo[q], 16, 0.5, co[q], 16, sp)
+
+    ms = _events_ms(torch, stream, calls, 5)
+    d = torch.from_numpy(iaat.descriptors(ps, base).view(np.uint8)).to(dev)
+    ms_b = _events_ms(torch, stream, lambda: iaat.iaat_gemm_vbatched_device(
+        h, d.data_ptr(), ps.count, stream=sp), 50)
+    fl = ps.flops()
+    return {"per_call_us": round(ms * 1e3 / ps.count, 3), "per_call_gflops": round(fl / ms / 1e6, 2),
+            "batched_us": round(ms_b * 1e3, 2), "batched_gflops": round(fl / ms_b / 1e6, 1)}
+
+
+def precision_leg(iaat, inputs, h, dev, stream):
+    """Reduced-precision inputs on the sweep grid (2 problems per shape,
+    |x| = 10^U(-3,3)): on-device quantisation and the batched GEMM, per type.
+    Bytes count A and B at the stored width (4 bytes for a bf16 hi/lo pair)."""
+    import numpy as np
+    import torch
+    ps = inputs.precision_problems(per_shape=2)
+    buf = torch.from_numpy(ps.buf).to(dev)
+    sp = stream.cuda_stream
+    fl = ps.flops()
+    m, n, k = (x.astype(np.float64) for x in (ps.m, ps.n, ps.k))
+    ab_elems = float(np.sum(m * k + k * n))
+    c_bytes = float(np.sum(4.0 * m * n * 2))  # beta = 1: C read and written
+    res = {"workload": "sweep grid x2 (%d problems), log-uniform entries" % ps.count}
+    for prec in (iaat.IAAT_PREC_BF16, iaat.IAAT_PREC_F16, iaat.IAAT_PREC_F8E4M3, iaat.IAAT_PREC_BF16X3):
+        eb = iaat.PREC_ELEM_BYTES[prec] * iaat.PREC_SPAN[prec]
+        codes = torch.zeros(iaat.PREC_SPAN[prec] * ps.buf.shape[0] * iaat.PREC_ELEM_BYTES[prec],
+                            dtype=torch.uint8, device=dev)
+        desc_dev = torch.zeros(ps.count * 64, dtype=torch.uint8, device=dev)
+        jobs, desc = iaat.lowp_layout(ps, prec, buf.data_ptr(), codes.data_ptr(), desc_dev.data_ptr())
+        desc_dev.copy_(torch.from_numpy(desc.view(np.uint8)))
+        jd = torch.from_numpy(jobs.view(np.uint8)).to(dev)
+        ms_q = _events_ms(torch, stream, lambda: iaat.iaat_quantize_batch(h, prec, jd.data_ptr(),
+                                                                            ps.count, sp), 3)
+        ms = _events_ms(torch, stream, lambda: iaat.iaat_gemm_vbatched_device(
+            h, desc_dev.data_ptr(), ps.count, prec=prec, stream=sp), 5)
+        gbs = (ab_elems * eb + c_bytes) / ms / 1e6
+        res[iaat.PREC_NAMES[prec]] = {"gemm_us": round(ms * 1e3, 1), "gflops": round(fl / ms / 1e6, 1),
+                                      "hbm_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                                      "quantize_us": round(ms_q * 1e3, 1)}
+        print("[bench] precision %s: %.1f us" % (iaat.PREC_NAMES[prec], ms * 1e3), file=sys.stderr,
+              flush=True)
+    return res
+
+
+def serve_leg(iaat, inputs, h, dev, seconds):
+    """Open-loop Poisson traces at 20k, 50k and 100k requests/s, 1..256 GEMMs
+    per request from a resident pool (sweep-grid shapes, alpha = beta = 1),
+    8 GB admission cap; latency = completion - scheduled arrival."""
+    import numpy as np
+    import torch
+    ps = inputs.serve_pool(16384)
+    buf = torch.from_numpy(ps.buf).to(dev)
+    desc = iaat.descriptors(ps, buf.data_ptr())
+    pf = 2.0 * ps.m.astype(np.float64) * ps.n * ps.k
+    res = {"pool_gemms": ps.count, "seconds": seconds, "mem_cap_gb": 8, "streams": 4}
+    for i, rate in enumerate((20000.0, 50000.0, 100000.0)):
+        t, cnt = inputs.poisson_trace(rate, seconds, seed=inputs.SEED_BASE + 4 + 10 * (i + 1))
+        idx = inputs.pool_indices(int(cnt.sum()), ps.count, seed=inputs.SEED_BASE + 5 + 10 * (i + 1))
+        srv = iaat.iaat_serve_start(h, 8 << 30, n_streams=4, max_batch_gemms=16384)
+        try:
+            lat = iaat.iaat_serve_replay(srv, t, cnt, idx, desc)
+            st = iaat.iaat_serve_stats_get(srv)
+        finally:
+            iaat.iaat_serve_stop(srv)
+        offered = float(pf[idx].sum()) / seconds / 1e9
+        res["%dk_req_s" % int(rate / 1000)] = {
+            "requests": int(t.shape[0]), "gemms": int(cnt.sum()),
+            "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+            "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+            "max_ms": round(float(lat.max()) * 1e3, 3),
+            "achieved_gflops": round(st["gflops"], 1), "offered_gflops": round(offered, 1),
+            "launches": st["launches"], "gemms_per_launch": round(st["gemms_done"] / max(st["launches"], 1), 1),
+            "peak_admitted_mb": round(st["peak_admitted_bytes"] / 2 ** 20, 1),
+            "peak_queue_depth": st["peak_queue_depth"], "failed": st["failed"]}
+        print("[bench] serve %dk req/s: p50 %.3f ms p99 %.3f ms" % (
+            rate / 1000, np.percentile(lat, 50) * 1e3, np.percentile(lat, 99) * 1e3),
+            file=sys.stderr, flush=True)
+    return res
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -75,6 +182,10 @@ def main() -> int:
                     help="only run a 1 GiB device-to-device copy (counter calibration)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-percall", action="store_true")
+    ap.add_argument("--no-precision", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=1.0,
+                    help="length of each open-loop serving trace (seconds)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -100,7 +211,7 @@ def main() -> int:
 
     if args.profile:
         args.steps, args.warmup = 5, 1
-        args.no_cpu_baseline = args.no_percall = True
+        args.no_cpu_baseline = args.no_percall = args.no_precision = args.no_serve = True
 
     t0 = time.time()
     ps = inputs.uneven_batch(args.count)
@@ -197,6 +308,13 @@ def main() -> int:
                              "speedup_of_value": round(value / (flops / ms_pc / 1e6), 1)}
         print("[bench] per-call: %.2f us/problem" % (ms_pc * 1e3 / ps.count), file=sys.stderr,
               flush=True)
+
+    if not args.no_percall:
+        extra["plain_nn16_1000"] = plain_nn16(iaat, inputs, ctx.handle, dev, stream)
+    if not args.no_precision:
+        extra["precision"] = precision_leg(iaat, inputs, ctx.handle, dev, stream)
+    if not args.no_serve:
+        extra["serve"] = serve_leg(iaat, inputs, ctx.handle, dev, args.serve_seconds)
 
     cpu = None
     if not args.no_cpu_baseline:
