@@ -6,6 +6,8 @@ boundary values.  Tiler: the 15 x 15 SGEMM_NN example of Section V-A
 (Fig. 2: 72K + 450 loads), the strip lower bound, Table 1's kernel counts,
 and cover/membership invariants over every M, N <= 80.
 """
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -97,16 +99,30 @@ def test_split_bf16_properties():
     assert rel.max() <= 2.0 ** -16
 
 
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def golden_rows(name):
+    rows = {}
+    for line in open(os.path.join(GOLDEN, name)):
+        line = line.split("#")[0].split()
+        if line:
+            rows[line[0]] = [int(x) for x in line[1:]]
+    return rows
+
+
 def test_fig2_fifteen_by_fifteen():
+    a, b = golden_rows("fig2_15x15_loads.txt")["iaat"]
     blocks = tiler_ref.sgemm_nn_tile(15, 15)
-    assert tiler_ref.memops_S(blocks) == 72
+    assert tiler_ref.memops_S(blocks) == a
     K = 37
-    assert tiler_ref.memops(blocks, 15, 15, K) == 72 * K + 450
-    assert tiler_ref.strip_dp_optimum(15, 15) == 72
+    assert tiler_ref.memops(blocks, 15, 15, K) == a * K + b
+    assert tiler_ref.strip_dp_optimum(15, 15) == a
 
 
 def test_table1_counts():
-    assert [tiler_ref.kernel_count(t) for t in "SDCZ"] == [290, 186, 210, 100]
+    want = golden_rows("table1_kernel_counts.txt")
+    assert [tiler_ref.kernel_count(t) for t in "SDCZ"] == [want[t][0] for t in "SDCZ"]
 
 
 @pytest.mark.parametrize("M", range(1, 81))
