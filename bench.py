@@ -227,6 +227,8 @@ def main() -> int:
     stream = torch.cuda.current_stream(dev)
     sp = stream.cuda_stream
     ctx = iaat.Context(0)
+    from paper_2208_09822_amd import autotune
+    tuned = autotune.apply(ctx.handle)  # the install-time autotuned tile table
     plan = iaat.iaat_vbplan_create(ctx.handle, desc_dev.data_ptr(), ps.count)
 
     # --- timed region: graph replays of the persistent batched launch
@@ -337,6 +339,7 @@ def main() -> int:
                    "shapes": "M,N,K ~ U{1..80}, cbrt(MNK)<=80 (<=32 for TN)",
                    "layouts": "NN/NT/TN/TT uniform", "values": "U[-1,1]",
                    "scalars": "alpha,beta ~ U[-2,2]", "form": "iaat_vbplan_launch (hipGraph)",
+                   "tile_table": "autotuned (%d plans from tables/gfx950.txt)" % tuned,
                    "gflop_per_step": round(flops / 1e9, 4),
                    "algorithmic_gb_per_step": round(alg_bytes / 1e9, 4)},
         "roofline": roof,

@@ -314,6 +314,19 @@ int iaat_plan_query(iaat_ctx_t ctx, int layout, int m, int n, iaat_block* out, i
  * as iaat_plan_query. */
 int iaat_default_plan(int layout, int m, int n, iaat_block* out, int cap);
 
+/* Tile-table editing (the install-time autotuner's interface).
+ * iaat_plan_set stages a plan for (layout, m, n): `blocks` (nblk <= 15
+ * entries; i0, j0, kid are used, rows/cols ignored) must cover the m x n
+ * exactly with kernels of the family -- the same check every loaded table
+ * passes -- else -5 (-1 ctx, -2 layout, -3 m, -4 n, -6 nblk).  Staged plans
+ * take effect at iaat_table_commit, which waits for the device to be idle
+ * and uploads the table (no work of this context may be queued meanwhile).
+ * iaat_table_save writes the table in use to `path` in the format
+ * iaat_create loads. */
+int iaat_plan_set(iaat_ctx_t ctx, int layout, int m, int n, const iaat_block* blocks, int nblk);
+int iaat_table_commit(iaat_ctx_t ctx);
+int iaat_table_save(iaat_ctx_t ctx, const char* path);
+
 /* Number of generated kernels in the library's family, and the description
  * of kernel `kid`: family (0 MFMA tile grid, 1 row strip, 2 column strip,
  * 3 K-split reduction), its two size parameters, and its block extent. */

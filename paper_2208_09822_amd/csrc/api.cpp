@@ -354,6 +354,51 @@ int iaat_default_plan(int layout, int m, int n, iaat_block* out, int cap) {
   return describe_plan(default_plan(layout, m, n), m, n, out, cap);
 }
 
+int iaat_plan_set(iaat_ctx_t ctx, int layout, int m, int n, const iaat_block* blocks, int nblk) {
+  if (!ctx) return fail(-1, "iaat_plan_set: ctx is NULL");
+  if (layout < 0 || layout > 3) return fail(-2, "iaat_plan_set: layout=%d", layout);
+  if (m < 1 || m > kSuper) return fail(-3, "iaat_plan_set: m=%d", m);
+  if (n < 1 || n > kSuper) return fail(-4, "iaat_plan_set: n=%d", n);
+  if (!blocks) return fail(-5, "iaat_plan_set: blocks is NULL");
+  if (nblk < 1 || nblk > kMaxBlocks) return fail(-6, "iaat_plan_set: nblk=%d", nblk);
+  PlanEntry e;
+  memset(&e, 0, sizeof e);
+  e.nblk = (uint32_t)nblk;
+  for (int b = 0; b < nblk; ++b) {
+    const iaat_block& x = blocks[b];
+    if (x.kid < 0 || x.kid >= IAAT_NUM_KIDS || x.i0 < 0 || x.i0 >= m || x.j0 < 0 || x.j0 >= n)
+      return fail(-5, "iaat_plan_set: block %d (kid %d at %d,%d)", b, x.kid, x.i0, x.j0);
+    e.blk[b] = pack_block(x.i0, x.j0, x.kid);
+  }
+  std::string why;
+  if (!check_plan(m, n, e, &why)) return fail(-5, "iaat_plan_set: %s", why.c_str());
+  if (ctx->staged.empty()) ctx->staged = ctx->table;
+  ctx->staged[plan_index(layout, m, n)] = e;
+  return IAAT_OK;
+}
+
+int iaat_table_commit(iaat_ctx_t ctx) {
+  if (!ctx) return fail(-1, "iaat_table_commit: ctx is NULL");
+  if (ctx->staged.empty()) return IAAT_OK;
+  DeviceGuard g(ctx->device);
+  hipError_t e = hipDeviceSynchronize();
+  if (e == hipSuccess)
+    e = hipMemcpy(ctx->table_dev, ctx->staged.data(), ctx->staged.size() * sizeof(PlanEntry),
+                  hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "iaat_table_commit: upload");
+  ctx->table.swap(ctx->staged);
+  ctx->staged.clear();
+  return IAAT_OK;
+}
+
+int iaat_table_save(iaat_ctx_t ctx, const char* path) {
+  if (!ctx) return fail(-1, "iaat_table_save: ctx is NULL");
+  if (!path || !*path) return fail(-2, "iaat_table_save: path is empty");
+  std::string why;
+  const int rc = save_table(path, ctx->table, &why);
+  return rc == 0 ? IAAT_OK : fail(rc, "%s", why.c_str());
+}
+
 int iaat_family_size(void) { return IAAT_NUM_KIDS; }
 
 int iaat_family_info(int kid, int32_t* family, int32_t* p1, int32_t* p2, int32_t* block_rows,

@@ -112,6 +112,9 @@ def lib():
                 "iaat_gemm_vbatched": (i32, [vp, vp, i64, i32, vp, vp]),
                 "iaat_vbplan_create": (i32, [vp, vp, i64, i32, vp, ctypes.POINTER(vp)]),
                 "iaat_quantize_batch": (i32, [vp, i32, vp, i64, vp]),
+                "iaat_plan_set": (i32, [vp, i32, i32, i32, ctypes.POINTER(IaatBlock), i32]),
+                "iaat_table_commit": (i32, [vp]),
+                "iaat_table_save": (i32, [vp, ctypes.c_char_p]),
                 "iaat_serve_start": (i32, [vp, ctypes.POINTER(ServeCfg), ctypes.POINTER(vp)]),
                 "iaat_serve_submit": (i32, [vp, vp, i64, ctypes.c_double, i32,
                                             ctypes.POINTER(ctypes.c_uint64)]),
@@ -276,6 +279,20 @@ def iaat_plan_query(ctx, layout, m, n):
 
 def iaat_default_plan(layout, m, n):
     return _blocks(lib().iaat_default_plan, int(layout), int(m), int(n))
+
+
+def iaat_plan_set(ctx, layout, m, n, blocks) -> None:
+    """blocks: sequence of (i0, j0, kid)."""
+    arr = (IaatBlock * len(blocks))(*[IaatBlock(i0, j0, 0, 0, kid) for (i0, j0, kid) in blocks])
+    _check(lib().iaat_plan_set(ctx, layout, m, n, arr, len(blocks)))
+
+
+def iaat_table_commit(ctx) -> None:
+    _check(lib().iaat_table_commit(ctx))
+
+
+def iaat_table_save(ctx, path: str) -> None:
+    _check(lib().iaat_table_save(ctx, path.encode()))
 
 
 def iaat_family_size() -> int:

@@ -117,3 +117,30 @@ def test_serve_arguments_rejected_before_device_work():
     assert lib.iaat_serve_poll(None, 1, None) == -1
     assert lib.iaat_serve_stop(None) == 0
     assert ctypes.sizeof(iaat.ServeCfg) == 24 and ctypes.sizeof(iaat.ReqStatus) == 40
+
+
+def test_tuned_table_file_is_valid():
+    """Every class of the committed tuning has a choice the tuner offers, and
+    the plans it implies cover every (layout, m, n) exactly with family kernels."""
+    from paper_2208_09822_amd import autotune
+    choices = autotune.load(autotune.DEFAULT_TABLE)
+    kids = autotune._kids()
+    infos = {k: iaat.iaat_family_info(k) for k in range(iaat.iaat_family_size())}
+    seen = set()
+    for layout in range(4):
+        for m in range(1, 81):
+            for n in range(1, 81):
+                key, offered = autotune.class_of(layout, m, n)
+                seen.add(key)
+                ch = choices[key]
+                assert ch in offered, (key, ch)
+                blocks = autotune.plan_for(ch, m, n, kids)
+                if blocks is None:
+                    continue
+                assert len(blocks) <= 15
+                cover = np.zeros((m, n), np.int32)
+                for (i0, j0, kid) in blocks:
+                    r, c = infos[kid]["rows"], infos[kid]["cols"]
+                    cover[i0:min(i0 + r, m), j0:min(j0 + c, n)] += 1
+                assert (cover == 1).all(), (layout, m, n, ch)
+    assert seen == set(choices)
