@@ -99,6 +99,40 @@ def plain_nn16(iaat, inputs, h, dev, stream):
             "batched_us": round(ms_b * 1e3, 2), "batched_gflops": round(fl / ms_b / 1e6, 1)}
 
 
+def strided_leg(iaat, h, dev, stream):
+    """Same-size batches (iaat_gemm_strided_batched, one shared plan) against
+    the same problems through the uneven batched kernel."""
+    import numpy as np
+    import torch
+    res = {}
+    sp = stream.cuda_stream
+    for (m, n, k, batch) in ((16, 16, 16, 65536), (32, 32, 32, 32768), (80, 80, 80, 8192)):
+        g = torch.Generator(device="cpu").manual_seed(m)
+        A = (torch.rand(batch * m * k, generator=g) * 2 - 1).to(dev)
+        B = (torch.rand(batch * k * n, generator=g) * 2 - 1).to(dev)
+        C = (torch.rand(batch * m * n, generator=g) * 2 - 1).to(dev)
+        ms = _events_ms(torch, stream, lambda: iaat.iaat_gemm_strided_batched(
+            h, 0, 0, m, n, k, 1.0, A.data_ptr(), m, m * k, B.data_ptr(), k, k * n, 1.0,
+            C.data_ptr(), m, m * n, batch, sp), 10)
+        d = np.zeros(batch, dtype=iaat.PROBLEM_DTYPE)
+        z = np.arange(batch, dtype=np.uint64)
+        d["A"] = A.data_ptr() + 4 * z * (m * k)
+        d["B"] = B.data_ptr() + 4 * z * (k * n)
+        d["C"] = C.data_ptr() + 4 * z * (m * n)
+        d["m"], d["n"], d["k"], d["lda"], d["ldb"], d["ldc"] = m, n, k, m, k, m
+        d["alpha"], d["beta"], d["ab_scale"] = 1.0, 1.0, 1.0
+        dd = torch.from_numpy(d.view(np.uint8)).to(dev)
+        mb = _events_ms(torch, stream, lambda: iaat.iaat_gemm_vbatched_device(
+            h, dd.data_ptr(), batch, stream=sp), 10)
+        byt = 4.0 * batch * (m * k + k * n + 2 * m * n)
+        fl = 2.0 * batch * m * n * k
+        res["nn%d_x%d" % (m, batch)] = {
+            "strided_us": round(ms * 1e3, 1), "strided_gbs": round(byt / ms / 1e6, 1),
+            "strided_gflops": round(fl / ms / 1e6, 1),
+            "vbatched_us": round(mb * 1e3, 1), "vbatched_gbs": round(byt / mb / 1e6, 1)}
+    return res
+
+
 def precision_leg(iaat, inputs, h, dev, stream):
     """Reduced-precision inputs on the sweep grid (2 problems per shape,
     |x| = 10^U(-3,3)): on-device quantisation and the batched GEMM, per type.
@@ -313,6 +347,8 @@ def main() -> int:
 
     if not args.no_percall:
         extra["plain_nn16_1000"] = plain_nn16(iaat, inputs, ctx.handle, dev, stream)
+    if not args.no_percall:
+        extra["strided_same_size"] = strided_leg(iaat, ctx.handle, dev, stream)
     if not args.no_precision:
         extra["precision"] = precision_leg(iaat, inputs, ctx.handle, dev, stream)
     if not args.no_serve:

@@ -116,6 +116,20 @@ int iaat_gemm(iaat_ctx_t ctx, int ta, int tb, int64_t m, int64_t n, int64_t k,
               float alpha, const float* A, int64_t lda, const float* B, int64_t ldb,
               float beta, float* C, int64_t ldc, iaat_stream_t stream);
 
+/* Same-size repeated problems (the case the closing remark of Section VI
+ * names as IAAT's best fit): `batch` problems of one shape and layout,
+ * problem z at A + z*stride_a, B + z*stride_b, C + z*stride_c (strides in
+ * elements).  One launch; the tile plan is looked up once and shared.
+ * Argument numbers: ta 2, tb 3, m 4, n 5, k 6, A 8, lda 9, stride_a 10,
+ * B 11, ldb 12, stride_b 13, C 15, ldc 16, stride_c 17, batch 18.  Strides
+ * are >= 0; when batch > 1, stride_c >= ldc*n (outputs must not overlap).
+ * Quick returns and NULL rules as iaat_gemm.  Does not allocate.  Results
+ * are bitwise those of iaat_gemm on each problem. */
+int iaat_gemm_strided_batched(iaat_ctx_t ctx, int ta, int tb, int64_t m, int64_t n, int64_t k,
+                              float alpha, const float* A, int64_t lda, int64_t stride_a,
+                              const float* B, int64_t ldb, int64_t stride_b, float beta, float* C,
+                              int64_t ldc, int64_t stride_c, int64_t batch, iaat_stream_t stream);
+
 /* ------------------------------------------------- many uneven problems */
 
 /* One problem of a batch: 64 bytes, naturally aligned. */

@@ -7,6 +7,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <atomic>
 #include <mutex>
 #include <string>
@@ -77,6 +78,20 @@ void free_ctx(iaat_ctx* c) {
 
 namespace iaat {
 
+// Blocks of the plan with the most blocks among the (at most four) distinct
+// super-block shapes of an m x n problem.
+static int max_plan_blocks(iaat_ctx_t ctx, int layout, int64_t m, int64_t n, int64_t nsm, int64_t nsn) {
+  const int lm = (int)(m - (nsm - 1) * kSuper), ln = (int)(n - (nsn - 1) * kSuper);
+  int maxb = 0;
+  const int ms[2] = {kSuper, lm}, ns[2] = {kSuper, ln};
+  for (int a = (nsm > 1 ? 0 : 1); a < 2; ++a)
+    for (int b = (nsn > 1 ? 0 : 1); b < 2; ++b) {
+      const int nb = (int)ctx->table[plan_index(layout, ms[a], ns[b])].nblk;
+      if (nb > maxb) maxb = nb;
+    }
+  return maxb;
+}
+
 // The batched launch(es) for one descriptor array: the staged FP32 kernel
 // and its companion, or the reduced-precision kernel.
 hipError_t launch_batch(iaat_ctx_t ctx, const iaat_problem* probs_dev, int64_t count, int prec,
@@ -142,6 +157,7 @@ int iaat_create(iaat_ctx_t* out, int device, const char* tile_table_path) {
   }
   c->vb_grid = per_cu * c->num_cu;
   c->direct_grid = direct_per_cu * c->num_cu;
+
   const size_t tbytes = sizeof(PlanEntry) * c->table.size();
   if (hipMalloc(&c->table_dev, tbytes) != hipSuccess) {
     free_ctx(c);
@@ -198,6 +214,46 @@ int iaat_gemm(iaat_ctx_t ctx, int ta, int tb, int64_t m, int64_t n, int64_t k, f
   dev::Prob P{A, B, C, (int)m, (int)n, (int)k, (int)lda, (int)ldb, (int)ldc, alpha, beta};
   e = launch_gemm_f32(P, layout, ctx->table_dev, (int)nsm, (int)nsn, maxb, s);
   return e == hipSuccess ? IAAT_OK : hip_fail(e, "iaat_gemm: launch");
+}
+
+int iaat_gemm_strided_batched(iaat_ctx_t ctx, int ta, int tb, int64_t m, int64_t n, int64_t k,
+                              float alpha, const float* A, int64_t lda, int64_t stride_a,
+                              const float* B, int64_t ldb, int64_t stride_b, float beta, float* C,
+                              int64_t ldc, int64_t stride_c, int64_t batch, iaat_stream_t stream) {
+  if (!ctx) return fail(-1, "iaat_gemm_strided_batched: ctx is NULL");
+  if (ta != IAAT_OP_N && ta != IAAT_OP_T) return fail(-2, "iaat_gemm_strided_batched: ta=%d", ta);
+  if (tb != IAAT_OP_N && tb != IAAT_OP_T) return fail(-3, "iaat_gemm_strided_batched: tb=%d", tb);
+  const int layout = ta | (tb << 1);
+  int st = validate(layout, m, n, k, lda, ldb, ldc, alpha, A, B, C);
+  // argument numbers of this entry point
+  static const int remap[15] = {0, 0, -2, -3, -4, -5, -6, 0, -8, -9, -11, -12, 0, -15, -16};
+  if (st != 0) {
+    st = remap[-st];
+    return fail(st, "iaat_gemm_strided_batched: invalid argument %d", -st);
+  }
+  if (batch < 0) return fail(-18, "iaat_gemm_strided_batched: batch=%lld", (long long)batch);
+  if (stride_a < 0) return fail(-10, "iaat_gemm_strided_batched: stride_a=%lld", (long long)stride_a);
+  if (stride_b < 0) return fail(-13, "iaat_gemm_strided_batched: stride_b=%lld", (long long)stride_b);
+  if (batch > 1 && m > 0 && n > 0 && stride_c < ldc * n)
+    return fail(-17, "iaat_gemm_strided_batched: stride_c=%lld < ldc*n (outputs overlap)",
+                (long long)stride_c);
+  if (m == 0 || n == 0 || batch == 0) return IAAT_OK;
+  DeviceGuard g(ctx->device);
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e;
+  if (alpha == 0.0f || k == 0) {
+    e = launch_scale_f32_strided(C, (int)m, (int)n, (int)ldc, beta, stride_c, batch, s);
+    return e == hipSuccess ? IAAT_OK : hip_fail(e, "iaat_gemm_strided_batched: scale launch");
+  }
+  const int64_t nsm = (m + kSuper - 1) / kSuper, nsn = (n + kSuper - 1) / kSuper;
+  if (nsm * nsn > 0x7fffffffLL)
+    return fail(IAAT_ERR_UNSUPPORTED, "iaat_gemm_strided_batched: %lld x %lld is too large",
+                (long long)m, (long long)n);
+  dev::Prob P{A, B, C, (int)m, (int)n, (int)k, (int)lda, (int)ldb, (int)ldc, alpha, beta};
+  e = launch_gemm_f32_strided(P, layout, ctx->table_dev, (int)nsm, (int)nsn,
+                              max_plan_blocks(ctx, layout, m, n, nsm, nsn), stride_a, stride_b,
+                              stride_c, batch, s);
+  return e == hipSuccess ? IAAT_OK : hip_fail(e, "iaat_gemm_strided_batched: launch");
 }
 
 int iaat_quantize_batch(iaat_ctx_t ctx, int prec, const iaat_qjob* jobs_dev, int64_t count,
@@ -388,6 +444,7 @@ int iaat_table_commit(iaat_ctx_t ctx) {
   if (e != hipSuccess) return hip_fail(e, "iaat_table_commit: upload");
   ctx->table.swap(ctx->staged);
   ctx->staged.clear();
+
   return IAAT_OK;
 }
 

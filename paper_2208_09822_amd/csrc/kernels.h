@@ -31,8 +31,14 @@ struct VbArgs {
 hipError_t launch_gemm_f32(const dev::Prob& P, int layout, const PlanEntry* table_dev, int nsm,
                            int nsn, int max_blocks, hipStream_t stream);
 hipError_t launch_scale_f32(float* C, int m, int n, int ldc, float beta, hipStream_t stream);
+hipError_t launch_gemm_f32_strided(const dev::Prob& P, int layout, const PlanEntry* table_dev, int nsm,
+                                   int nsn, int max_blocks, int64_t sa, int64_t sb, int64_t sc,
+                                   int64_t batch, hipStream_t stream);
+hipError_t launch_scale_f32_strided(float* C, int m, int n, int ldc, float beta, int64_t sc,
+                                    int64_t batch, hipStream_t stream);
 hipError_t launch_vbatched_f32(const VbArgs& a, int grid, int direct_grid, hipStream_t stream);
 hipError_t vbatched_occupancy(int* blocks_per_cu, int* direct_per_cu);
+
 
 // Copies float spans (src, dst, n floats), one work-group per span.
 struct CopySpan {

@@ -92,6 +92,40 @@ __global__ __launch_bounds__(64) void scale_kernel(float* C, int m, int n, int l
   scale_columns(C, m, n, ldc, beta, (int)blockIdx.x, (int)gridDim.x);
 }
 
+// Same-size batch: problem z has operands at A + z*sa, B + z*sb, C + z*sc;
+// grid.z walks the problems (grid-stride), grid.x/y as in gemm_f32_kernel,
+// with the one plan every problem shares.
+template <int TA, int TB>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4))) void gemm_f32_strided_kernel(
+    Prob P, int64_t sa, int64_t sb, int64_t sc, int64_t batch, const PlanEntry* __restrict__ table,
+    int nsn) {
+  const int sbk = blockIdx.x, b = blockIdx.y;
+  const int sbi = sbk / nsn, sbj = sbk - sbi * nsn;
+  const bool nar = narrow(P);
+  const PlanEntry* e = table + plan_index(TA | (TB << 1), sub_problem<TA, TB>(P, sbi, sbj).m,
+                                          sub_problem<TA, TB>(P, sbi, sbj).n);
+  if (nar ? b >= (int)e->nblk : b > 0) return;
+  for (int64_t z = blockIdx.z; z < batch; z += gridDim.z) {
+    Prob Q = P;
+    Q.A += z * sa;
+    Q.B += z * sb;
+    Q.C += z * sc;
+    const Prob S = sub_problem<TA, TB>(Q, sbi, sbj);
+    if (!nar) {
+      wide_subproblem<TA, TB>(S);
+      continue;
+    }
+    const uint32_t w = e->blk[b];
+    run_block<TA, TB>(blk_kid(w), S, blk_i0(w), blk_j0(w));
+  }
+}
+
+__global__ __launch_bounds__(64) void scale_strided_kernel(float* C, int m, int n, int ldc, float beta,
+                                                           int64_t sc, int64_t batch) {
+  for (int64_t z = blockIdx.y; z < batch; z += gridDim.y)
+    scale_columns(C + z * sc, m, n, ldc, beta, (int)blockIdx.x, (int)gridDim.x);
+}
+
 // ---------------------------------------------------------------------------
 // Batched path: one work-group of four wavefronts per problem.
 
@@ -597,6 +631,27 @@ hipError_t launch_gemm_f32(const dev::Prob& P, int layout, const PlanEntry* tabl
     case 2: hipLaunchKernelGGL((dev::gemm_f32_kernel<0, 1>), grid, block, 0, stream, P, table_dev, nsn); break;
     default: hipLaunchKernelGGL((dev::gemm_f32_kernel<1, 1>), grid, block, 0, stream, P, table_dev, nsn); break;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_f32_strided(const dev::Prob& P, int layout, const PlanEntry* table_dev, int nsm,
+                                   int nsn, int max_blocks, int64_t sa, int64_t sb, int64_t sc,
+                                   int64_t batch, hipStream_t stream) {
+  const unsigned gz = (unsigned)(batch < 65535 ? batch : 65535);
+  const dim3 grid((unsigned)(nsm * nsn), (unsigned)max_blocks, gz), block(64);
+  switch (layout) {
+    case 0: hipLaunchKernelGGL((dev::gemm_f32_strided_kernel<0, 0>), grid, block, 0, stream, P, sa, sb, sc, batch, table_dev, nsn); break;
+    case 1: hipLaunchKernelGGL((dev::gemm_f32_strided_kernel<1, 0>), grid, block, 0, stream, P, sa, sb, sc, batch, table_dev, nsn); break;
+    case 2: hipLaunchKernelGGL((dev::gemm_f32_strided_kernel<0, 1>), grid, block, 0, stream, P, sa, sb, sc, batch, table_dev, nsn); break;
+    default: hipLaunchKernelGGL((dev::gemm_f32_strided_kernel<1, 1>), grid, block, 0, stream, P, sa, sb, sc, batch, table_dev, nsn); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_f32_strided(float* C, int m, int n, int ldc, float beta, int64_t sc,
+                                    int64_t batch, hipStream_t stream) {
+  const unsigned gx = (unsigned)(n < 64 ? n : 64), gy = (unsigned)(batch < 65535 ? batch : 65535);
+  hipLaunchKernelGGL(dev::scale_strided_kernel, dim3(gx, gy), dim3(64), 0, stream, C, m, n, ldc, beta, sc, batch);
   return hipGetLastError();
 }
 

@@ -112,6 +112,8 @@ def lib():
                 "iaat_gemm_vbatched": (i32, [vp, vp, i64, i32, vp, vp]),
                 "iaat_vbplan_create": (i32, [vp, vp, i64, i32, vp, ctypes.POINTER(vp)]),
                 "iaat_quantize_batch": (i32, [vp, i32, vp, i64, vp]),
+                "iaat_gemm_strided_batched": (i32, [vp, i32, i32, i64, i64, i64, f32, vp, i64, i64,
+                                                    vp, i64, i64, f32, vp, i64, i64, i64, vp]),
                 "iaat_plan_set": (i32, [vp, i32, i32, i32, ctypes.POINTER(IaatBlock), i32]),
                 "iaat_table_commit": (i32, [vp]),
                 "iaat_table_save": (i32, [vp, ctypes.c_char_p]),
@@ -179,6 +181,13 @@ def iaat_gemm_vbatched(ctx, probs_host: np.ndarray, count=None, prec=IAAT_PREC_F
     count = len(arr) if count is None else int(count)
     _check(lib().iaat_gemm_vbatched(ctx, arr.ctypes.data if count else None, count, int(prec),
                                     status or None, stream or None))
+
+
+def iaat_gemm_strided_batched(ctx, ta, tb, m, n, k, alpha, A, lda, stride_a, B, ldb, stride_b,
+                              beta, C, ldc, stride_c, batch, stream=0) -> None:
+    _check(lib().iaat_gemm_strided_batched(ctx, ta, tb, m, n, k, alpha, A or None, lda, stride_a,
+                                           B or None, ldb, stride_b, beta, C or None, ldc,
+                                           stride_c, batch, stream or None))
 
 
 def iaat_quantize_batch(ctx, prec, jobs_dev, count, stream=0) -> None:

@@ -144,3 +144,16 @@ def test_tuned_table_file_is_valid():
                     cover[i0:min(i0 + r, m), j0:min(j0 + c, n)] += 1
                 assert (cover == 1).all(), (layout, m, n, ch)
     assert seen == set(choices)
+
+
+def test_strided_batched_null_context():
+    lib = iaat.lib()
+    assert lib.iaat_gemm_strided_batched(None, 0, 0, 4, 4, 4, 1.0, None, 4, 16, None, 4, 16, 0.0,
+                                         None, 4, 16, 2, None) == -1
+
+
+def test_library_has_no_unresolved_internal_symbols():
+    out = subprocess.run(["nm", "-D", "--undefined-only", iaat.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    bad = [l.split()[-1] for l in out.splitlines() if "iaat" in l]
+    assert not bad, bad
