@@ -217,6 +217,28 @@ int iaat_vbplan_create(iaat_ctx_t ctx, const iaat_problem* probs_dev, int64_t co
 int iaat_vbplan_launch(iaat_vbplan_t plan, iaat_stream_t stream);
 int iaat_vbplan_destroy(iaat_vbplan_t plan); /* NULL accepted */
 
+/* ------------------------------------------------ ablation: traditional */
+
+/* The traditional small-GEMM scheme that IAAT replaces (Section I; Fig. 2(a)
+ * against Section V), for measuring what the pack step and boundary
+ * handling cost on this GPU.  iaat_trad_create validates a batch (host
+ * descriptors, FP32; -2 names the first invalid problem) and allocates a
+ * workspace for its packed operands.  iaat_trad_pack copies every op(A) and
+ * op(B) into zero-padded, tile-contiguous buffers (rows, columns and K
+ * rounded up to 16); iaat_trad_compute then runs one uniform 16 x 16
+ * matrix-core tile per wavefront over them, masking only the C store.
+ * Pack must precede compute on the stream; the operands must not change in
+ * between.  Results meet the same tolerance as the IAAT path (the order of
+ * the K sum differs).  For the ablation only: iaat_gemm_vbatched* is the
+ * path to use. */
+typedef struct iaat_tradplan* iaat_tradplan_t;
+int iaat_trad_create(iaat_ctx_t ctx, const iaat_problem* probs_host, int64_t count,
+                     iaat_tradplan_t* out);
+int iaat_trad_pack(iaat_tradplan_t plan, iaat_stream_t stream);
+int iaat_trad_compute(iaat_tradplan_t plan, iaat_stream_t stream);
+int64_t iaat_trad_workspace_bytes(iaat_tradplan_t plan);
+int iaat_trad_destroy(iaat_tradplan_t plan); /* NULL accepted */
+
 /* ---------------------------------------------------------------- serving */
 
 /* A request loop over the batched form (continuous batching).  Requests

@@ -256,6 +256,107 @@ int iaat_gemm_strided_batched(iaat_ctx_t ctx, int ta, int tb, int64_t m, int64_t
   return e == hipSuccess ? IAAT_OK : hip_fail(e, "iaat_gemm_strided_batched: launch");
 }
 
+struct iaat_tradplan {
+  iaat_ctx* ctx = nullptr;
+  TradProb* probs = nullptr;
+  int32_t* tiles = nullptr;
+  float* work = nullptr;
+  int64_t count = 0, ntiles = 0, work_floats = 0;
+};
+
+int iaat_trad_destroy(iaat_tradplan_t p) {
+  if (!p) return IAAT_OK;
+  DeviceGuard g(p->ctx->device);
+  if (p->probs) (void)hipFree(p->probs);
+  if (p->tiles) (void)hipFree(p->tiles);
+  if (p->work) (void)hipFree(p->work);
+  delete p;
+  return IAAT_OK;
+}
+
+int iaat_trad_create(iaat_ctx_t ctx, const iaat_problem* probs_host, int64_t count,
+                     iaat_tradplan_t* out) {
+  if (!ctx) return fail(-1, "iaat_trad_create: ctx is NULL");
+  if (count < 0 || (count > 0 && !probs_host)) return fail(-2, "iaat_trad_create: no problems");
+  if (!out) return fail(-4, "iaat_trad_create: out is NULL");
+  *out = nullptr;
+  std::vector<TradProb> tp((size_t)count);
+  std::vector<int32_t> tiles;
+  int64_t work = 0;
+  for (int64_t q = 0; q < count; ++q) {
+    const iaat_problem& d = probs_host[q];
+    const int st = validate(d.trans, d.m, d.n, d.k, d.lda, d.ldb, d.ldc, d.alpha, d.A, d.B, d.C);
+    if (st != 0) return fail(-2, "iaat_trad_create: problem %lld: argument %d invalid", (long long)q, -st);
+    if (d.m > 0x3fffffff / 16 || q > 0x7fffffff)
+      return fail(IAAT_ERR_UNSUPPORTED, "iaat_trad_create: problem %lld too large", (long long)q);
+    TradProb& P = tp[(size_t)q];
+    P.A = (const float*)d.A;
+    P.B = (const float*)d.B;
+    P.C = d.C;
+    P.m = d.m; P.n = d.n; P.k = d.k;
+    P.lda = d.lda; P.ldb = d.ldb; P.ldc = d.ldc;
+    P.trans = d.trans;
+    P.alpha = d.alpha * d.ab_scale;
+    P.beta = d.beta;
+    P.m16 = (d.m + 15) / 16 * 16;
+    P.n16 = (d.n + 15) / 16 * 16;
+    P.k16 = (P.alpha == 0.0f) ? 0 : (d.k + 15) / 16 * 16;
+    P.a_off = work;
+    work += ((int64_t)P.m16 * P.k16 + 63) / 64 * 64;
+    P.b_off = work;
+    work += ((int64_t)P.n16 * P.k16 + 63) / 64 * 64;
+    for (int ti = 0; ti < P.m16 / 16; ++ti)
+      for (int tj = 0; tj < P.n16 / 16; ++tj) {
+        tiles.push_back((int32_t)q);
+        tiles.push_back(ti);
+        tiles.push_back(tj);
+      }
+  }
+  DeviceGuard g(ctx->device);
+  iaat_tradplan* p = new iaat_tradplan;
+  p->ctx = ctx;
+  p->count = count;
+  p->ntiles = (int64_t)tiles.size() / 3;
+  p->work_floats = work;
+  hipError_t e = hipSuccess;
+  if (count > 0) e = hipMalloc(&p->probs, tp.size() * sizeof(TradProb));
+  if (e == hipSuccess && p->ntiles > 0) e = hipMalloc(&p->tiles, tiles.size() * sizeof(int32_t));
+  if (e == hipSuccess && work > 0) e = hipMalloc(&p->work, work * sizeof(float));
+  if (e == hipSuccess && count > 0)
+    e = hipMemcpy(p->probs, tp.data(), tp.size() * sizeof(TradProb), hipMemcpyHostToDevice);
+  if (e == hipSuccess && p->ntiles > 0)
+    e = hipMemcpy(p->tiles, tiles.data(), tiles.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    iaat_trad_destroy(p);
+    return fail(IAAT_ERR_NOMEM, "iaat_trad_create: workspace of %lld floats: %s", (long long)work,
+                hipGetErrorString(e));
+  }
+  *out = p;
+  return IAAT_OK;
+}
+
+int64_t iaat_trad_workspace_bytes(iaat_tradplan_t p) { return p ? p->work_floats * 4 : 0; }
+
+int iaat_trad_pack(iaat_tradplan_t p, iaat_stream_t stream) {
+  if (!p) return fail(-1, "iaat_trad_pack: plan is NULL");
+  if (p->count == 0 || p->work_floats == 0) return IAAT_OK;
+  DeviceGuard g(p->ctx->device);
+  const int64_t cap = 8LL * p->ctx->num_cu;
+  const hipError_t e = launch_trad_pack(p->probs, p->count, p->work,
+                                        (int)(p->count < cap ? p->count : cap), (hipStream_t)stream);
+  return e == hipSuccess ? IAAT_OK : hip_fail(e, "iaat_trad_pack: launch");
+}
+
+int iaat_trad_compute(iaat_tradplan_t p, iaat_stream_t stream) {
+  if (!p) return fail(-1, "iaat_trad_compute: plan is NULL");
+  if (p->ntiles == 0) return IAAT_OK;
+  DeviceGuard g(p->ctx->device);
+  const int64_t cap = 64LL * p->ctx->num_cu;
+  const hipError_t e = launch_trad_tiles(p->probs, p->tiles, p->ntiles, p->work,
+                                         (int)(p->ntiles < cap ? p->ntiles : cap), (hipStream_t)stream);
+  return e == hipSuccess ? IAAT_OK : hip_fail(e, "iaat_trad_compute: launch");
+}
+
 int iaat_quantize_batch(iaat_ctx_t ctx, int prec, const iaat_qjob* jobs_dev, int64_t count,
                         iaat_stream_t stream) {
   if (!ctx) return fail(-1, "iaat_quantize_batch: ctx is NULL");

@@ -48,6 +48,21 @@ struct CopySpan {
 };
 hipError_t launch_copy_spans(const CopySpan* spans, int64_t count, int grid, hipStream_t stream);
 
+// Traditional pack + uniform-tile scheme (traditional.hip), for ablation.
+struct TradProb {
+  const float* A;
+  const float* B;
+  float* C;
+  int64_t a_off, b_off;  // packed op(A) / op(B) in the workspace, in floats
+  int m, n, k, lda, ldb, ldc, trans;
+  int m16, n16, k16;     // sizes rounded up to 16 (k16 = 0 when A and B are not read)
+  float alpha, beta;
+};
+hipError_t launch_trad_pack(const TradProb* probs, int64_t count, float* work, int grid,
+                            hipStream_t stream);
+hipError_t launch_trad_tiles(const TradProb* probs, const int32_t* tiles, int64_t ntiles,
+                             const float* work, int grid, hipStream_t stream);
+
 // Reduced-precision inputs (precision.hip).
 hipError_t launch_quantize(int prec, const iaat_qjob* jobs, int64_t count, int grid, hipStream_t stream);
 hipError_t launch_vbatched_lowp(const VbArgs& a, int prec, int grid, hipStream_t stream);

@@ -112,6 +112,11 @@ def lib():
                 "iaat_gemm_vbatched": (i32, [vp, vp, i64, i32, vp, vp]),
                 "iaat_vbplan_create": (i32, [vp, vp, i64, i32, vp, ctypes.POINTER(vp)]),
                 "iaat_quantize_batch": (i32, [vp, i32, vp, i64, vp]),
+                "iaat_trad_create": (i32, [vp, vp, i64, ctypes.POINTER(vp)]),
+                "iaat_trad_pack": (i32, [vp, vp]),
+                "iaat_trad_compute": (i32, [vp, vp]),
+                "iaat_trad_workspace_bytes": (i64, [vp]),
+                "iaat_trad_destroy": (i32, [vp]),
                 "iaat_gemm_strided_batched": (i32, [vp, i32, i32, i64, i64, i64, f32, vp, i64, i64,
                                                     vp, i64, i64, f32, vp, i64, i64, i64, vp]),
                 "iaat_plan_set": (i32, [vp, i32, i32, i32, ctypes.POINTER(IaatBlock), i32]),
@@ -188,6 +193,29 @@ def iaat_gemm_strided_batched(ctx, ta, tb, m, n, k, alpha, A, lda, stride_a, B, 
     _check(lib().iaat_gemm_strided_batched(ctx, ta, tb, m, n, k, alpha, A or None, lda, stride_a,
                                            B or None, ldb, stride_b, beta, C or None, ldc,
                                            stride_c, batch, stream or None))
+
+
+def iaat_trad_create(ctx, probs_host: np.ndarray) -> int:
+    d = np.ascontiguousarray(probs_host, dtype=PROBLEM_DTYPE)
+    h = ctypes.c_void_p()
+    _check(lib().iaat_trad_create(ctx, d.ctypes.data, d.shape[0], ctypes.byref(h)))
+    return h.value
+
+
+def iaat_trad_pack(plan, stream=0) -> None:
+    _check(lib().iaat_trad_pack(plan, stream or None))
+
+
+def iaat_trad_compute(plan, stream=0) -> None:
+    _check(lib().iaat_trad_compute(plan, stream or None))
+
+
+def iaat_trad_workspace_bytes(plan) -> int:
+    return lib().iaat_trad_workspace_bytes(plan)
+
+
+def iaat_trad_destroy(plan) -> None:
+    _check(lib().iaat_trad_destroy(plan))
 
 
 def iaat_quantize_batch(ctx, prec, jobs_dev, count, stream=0) -> None:
