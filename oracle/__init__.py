@@ -8,7 +8,8 @@ code with it: no kernels, headers, helpers, tables or generators.
 
 Contents
   gemm_f64.c   FP64 triple-loop GEMM (Section I statement, Table 1 note for the
-               layouts), built with gcc into ``_build/liboracle.so``.
+               layouts) for FP32 inputs, and the same loop with FP64 operands
+               (DGEMM, Table 1 row D), built with gcc into ``_build/liboracle.so``.
   quant.py     BF16 / FP16 / FP8-E4M3 rounding from the format definitions,
                the split-BF16 pair, the power-of-two FP8 scale.
   tiler_ref.py A reading of the SGEMM_NN tile algorithm (Section V-A,
@@ -59,6 +60,8 @@ def _load():
             lib.oracle_gemm_f64.restype = None
             lib.oracle_gemm_f64_d.argtypes = lib.oracle_gemm_f64.argtypes
             lib.oracle_gemm_f64_d.restype = None
+            lib.oracle_dgemm.argtypes = lib.oracle_gemm_f64.argtypes
+            lib.oracle_dgemm.restype = None
             lib.oracle_gemm_batch.argtypes = [i64] + [vp] * 15 + [i32]
             lib.oracle_gemm_batch.restype = dbl
             _lib = lib
@@ -98,6 +101,19 @@ def gemm_dequant(ta, tb, m, n, k, alpha, A64, lda, B64, ldb, beta, C0, ldc):
     if m > 0 and n > 0:
         lib.oracle_gemm_f64_d(int(ta), int(tb), m, n, k, float(alpha), _ptr(a), lda,
                               _ptr(b), ldb, float(beta), _ptr(c), ldc, _ptr(out), max(m, 1))
+    return out[:n, :m].T.copy()
+
+
+def dgemm(ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C0, ldc):
+    """DGEMM (Table 1, row D): FP64 operands and C0, FP64 result (m x n)."""
+    lib = _load()
+    out = np.zeros((max(n, 1), max(m, 1)), dtype=np.float64)
+    a = None if A is None else np.ascontiguousarray(A, dtype=np.float64)
+    b = None if B is None else np.ascontiguousarray(B, dtype=np.float64)
+    c = None if C0 is None else np.ascontiguousarray(C0, dtype=np.float64)
+    if m > 0 and n > 0:
+        lib.oracle_dgemm(int(ta), int(tb), m, n, k, float(alpha), _ptr(a), lda, _ptr(b), ldb,
+                         float(beta), _ptr(c), ldc, _ptr(out), max(m, 1))
     return out[:n, :m].T.copy()
 
 

@@ -119,6 +119,33 @@ static void* batch_worker(void* arg)
 }
 
 /* Runs the batch on nthreads POSIX threads; returns wall seconds. */
+/* DGEMM (Table 1, row D): the same definition with every operand, C0
+ * included, in FP64.  C0 is not read when beta == 0; A and B are not read
+ * when alpha == 0 or k == 0. */
+void oracle_dgemm(int ta, int tb, int64_t m, int64_t n, int64_t k,
+                  double alpha, const double* A, int64_t lda,
+                  const double* B, int64_t ldb,
+                  double beta, const double* C0, int64_t ldc,
+                  double* out, int64_t ldo)
+{
+    for (int64_t j = 0; j < n; ++j) {
+        for (int64_t i = 0; i < m; ++i) {
+            double s = 0.0;
+            if (alpha != 0.0 && k > 0) {
+                for (int64_t p = 0; p < k; ++p) {
+                    double a = ta ? A[p + i * lda] : A[i + p * lda];
+                    double b = tb ? B[j + p * ldb] : B[p + j * ldb];
+                    s += a * b;
+                }
+            }
+            double r = alpha * s;
+            if (beta != 0.0)
+                r += beta * C0[i + j * ldc];
+            out[i + j * ldo] = r;
+        }
+    }
+}
+
 double oracle_gemm_batch(int64_t count, const int32_t* trans,
                          const int32_t* m, const int32_t* n, const int32_t* k,
                          const int32_t* lda, const int32_t* ldb, const int32_t* ldc,

@@ -190,3 +190,66 @@ def test_batch_driver_matches_single_calls():
                              float(ps.beta[q]), ps.C(q), int(ps.ldc[q]))
         got = out[off[q]:off[q] + M * N].reshape(N, M).T
         assert np.array_equal(single, got)
+
+
+# ---- DGEMM (FP64 operands): pinned independently of the FP32-input loop
+
+def _rand64(rng, shape):
+    return rng.uniform(-1, 1, shape)
+
+
+def test_dgemm_identity_and_rank_one():
+    rng = np.random.Generator(np.random.PCG64(901))
+    m, n = 7, 5
+    B = _rand64(rng, (m, n))
+    C0 = _rand64(rng, (m, n))
+    got = oracle.dgemm(0, 0, m, n, m, 1.5, np.eye(m).ravel(order="F"), m, B.ravel(order="F"), m,
+                       -0.5, C0.ravel(order="F"), m)
+    assert np.array_equal(got, 1.5 * B - 0.5 * C0)
+    x = rng.integers(-4, 5, m).astype(np.float64)
+    y = rng.integers(-4, 5, n).astype(np.float64)
+    K = 9
+    A = np.outer(x, np.ones(K))
+    Bm = np.outer(np.ones(K), y)
+    got = oracle.dgemm(0, 0, m, n, K, 2.0, A.ravel(order="F"), m, Bm.ravel(order="F"), K, 0.0,
+                       None, m)
+    assert np.array_equal(got, 2.0 * K * np.outer(x, y))
+
+
+def test_dgemm_quick_returns_and_nan_rules():
+    m, n, k = 3, 4, 5
+    A = np.full(m * k, np.nan)
+    C0 = np.arange(m * n, dtype=np.float64)
+    got = oracle.dgemm(0, 0, m, n, k, 0.0, A, m, A, k, 2.0, C0, m)
+    assert np.array_equal(got, 2.0 * C0.reshape(n, m).T)
+    ones = np.ones(m * k)
+    got = oracle.dgemm(0, 0, m, n, k, 1.0, ones, m, np.ones(k * n), k, 0.0, np.full(m * n, np.nan), m)
+    assert np.array_equal(got, np.full((m, n), float(k)))
+
+
+@pytest.mark.parametrize("lay", ["NN", "NT", "TN", "TT"])
+def test_dgemm_against_numpy_and_layouts(lay):
+    rng = np.random.Generator(np.random.PCG64(902))
+    m, n, k = 13, 11, 17
+    Aop = _rand64(rng, (m, k))
+    Bop = _rand64(rng, (k, n))
+    C0 = _rand64(rng, (m, n))
+    ta, tb = lay[0] == "T", lay[1] == "T"
+    A = (Aop.T if ta else Aop).ravel(order="F")
+    B = (Bop.T if tb else Bop).ravel(order="F")
+    got = oracle.dgemm(int(ta), int(tb), m, n, k, 0.75, A, k if ta else m, B, n if tb else k,
+                       1.25, C0.ravel(order="F"), m)
+    ref = 0.75 * (Aop @ Bop) + 1.25 * C0
+    assert np.linalg.norm(got - ref) <= (k + 2) * 2.0 ** -52 * np.linalg.norm(
+        0.75 * np.abs(Aop) @ np.abs(Bop) + 1.25 * np.abs(C0))
+
+
+def test_dgemm_brute_force_tiny():
+    vals = (-1.0, 0.0, 1.0)
+    for m, n, k in [(1, 1, 1), (1, 2, 2), (2, 1, 2), (2, 2, 1)]:
+        for a in itertools.product(vals, repeat=m * k):
+            b = np.array([1.0, -1.0][:k * n] + [0.0] * max(0, k * n - 2))
+            got = oracle.dgemm(0, 0, m, n, k, 1.0, np.array(a), m, b, k, 0.0, None, m)
+            for i in range(m):
+                for j in range(n):
+                    assert got[i, j] == sum(a[i + p * m] * b[p + j * k] for p in range(k))
