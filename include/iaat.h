@@ -130,6 +130,20 @@ int iaat_gemm_strided_batched(iaat_ctx_t ctx, int ta, int tb, int64_t m, int64_t
                               const float* B, int64_t ldb, int64_t stride_b, float beta, float* C,
                               int64_t ldc, int64_t stride_c, int64_t batch, iaat_stream_t stream);
 
+/* DGEMM (Table 1, row D): the same operation in FP64 (operands, scalars,
+ * C and accumulation), on the FP64 matrix cores.  C's 16 x 16 tiles are
+ * grouped into blocks of at most 3 x 3 tiles (one wavefront each), operands
+ * read in place.  Argument numbers, quick returns and NULL rules as
+ * iaat_gemm / iaat_gemm_strided_batched.  Does not allocate. */
+int iaat_dgemm(iaat_ctx_t ctx, int ta, int tb, int64_t m, int64_t n, int64_t k, double alpha,
+               const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
+               int64_t ldc, iaat_stream_t stream);
+int iaat_dgemm_strided_batched(iaat_ctx_t ctx, int ta, int tb, int64_t m, int64_t n, int64_t k,
+                               double alpha, const double* A, int64_t lda, int64_t stride_a,
+                               const double* B, int64_t ldb, int64_t stride_b, double beta,
+                               double* C, int64_t ldc, int64_t stride_c, int64_t batch,
+                               iaat_stream_t stream);
+
 /* ------------------------------------------------- many uneven problems */
 
 /* One problem of a batch: 64 bytes, naturally aligned. */

@@ -48,6 +48,19 @@ struct CopySpan {
 };
 hipError_t launch_copy_spans(const CopySpan* spans, int64_t count, int grid, hipStream_t stream);
 
+// DGEMM (dgemm.hip): one problem (or a same-size strided batch).
+struct DProb {
+  const double* A;
+  const double* B;
+  double* C;
+  int m, n, k, lda, ldb, ldc;
+  double alpha, beta;
+};
+hipError_t launch_dgemm(const DProb& P, int layout, int64_t sa, int64_t sb, int64_t sc, int64_t batch,
+                        hipStream_t stream);
+hipError_t launch_dscale(double* C, int m, int n, int64_t ldc, double beta, int64_t sc, int64_t batch,
+                         hipStream_t stream);
+
 // Traditional pack + uniform-tile scheme (traditional.hip), for ablation.
 struct TradProb {
   const float* A;

@@ -157,3 +157,8 @@ def test_library_has_no_unresolved_internal_symbols():
                          text=True, check=True).stdout
     bad = [l.split()[-1] for l in out.splitlines() if "iaat" in l]
     assert not bad, bad
+
+
+def test_dgemm_null_context():
+    lib = iaat.lib()
+    assert lib.iaat_dgemm(None, 0, 0, 4, 4, 4, 1.0, None, 4, None, 4, 0.0, None, 4, None) == -1
