@@ -39,13 +39,13 @@ struct Req {
   bool keep = false, released = false;
 };
 
+// One launch slot.  Its staging buffer holds the launch's descriptors, then
+// its output-seeding copy spans, so one upload carries both.
 struct Launch {
+  char* stage_host = nullptr;  // pinned
+  char* stage_dev = nullptr;
   iaat_problem* desc_host = nullptr;
-  iaat_problem* desc_dev = nullptr;
-  int32_t* st_host = nullptr;
-  int32_t* st_dev = nullptr;
   CopySpan* cp_host = nullptr;
-  CopySpan* cp_dev = nullptr;
   hipEvent_t ev = nullptr;
   hipStream_t stream = nullptr;
   bool busy = false;
@@ -144,12 +144,9 @@ struct iaat_server {
       const hipError_t q = hipEventQuery(L.ev);
       if (q == hipErrorNotReady) continue;
       const double t = now();
-      for (size_t r = 0; r < L.tickets.size(); ++r) {
-        Req& R = reqs[L.tickets[r] - 1];
-        int err = q == hipSuccess ? 0 : IAAT_ERR_HIP;
-        for (int64_t i = 0; i < R.n && err == 0; ++i) err = L.st_host[L.first[r] + i];
-        finish(R, err, t);
-      }
+      // every GEMM was validated at submit, so a launch fails only as a whole
+      for (size_t r = 0; r < L.tickets.size(); ++r)
+        finish(reqs[L.tickets[r] - 1], q == hipSuccess ? 0 : IAAT_ERR_HIP, t);
       L.tickets.clear();
       L.first.clear();
       L.busy = false;
@@ -160,14 +157,29 @@ struct iaat_server {
     return any;
   }
 
+  int64_t queued_gemms = 0;  // GEMMs of the requests waiting for admission
+
+  // Continuous batching: with nothing in flight a request is launched at
+  // once; while launches are in flight, the next one waits until a quarter
+  // of a full launch has queued up or the oldest queued request has waited
+  // kBatchWait, so the launch count (and its per-launch host cost) stays
+  // bounded under heavy load.
+  static constexpr double kBatchWait = 40e-6;
+  bool launch_now() const {
+    if (queue.empty()) return false;
+    if (in_flight == 0 || queued_gemms >= cfg.max_batch_gemms / 4) return true;
+    return now() - reqs[queue.front() - 1].t_arrival >= kBatchWait;
+  }
+
   // Admits queued requests into free launch slots and launches them.
   // Caller holds lk; it is released around the HIP calls.
   bool admit(std::unique_lock<std::mutex>& lk) {
     bool any = false;
     for (Launch& L : slots) {
-      if (L.busy || queue.empty()) continue;
-      int64_t n = 0, ncp = 0;
+      if (L.busy || !launch_now()) continue;
+      int64_t n = 0;
       const double t = now();
+      std::vector<std::pair<float*, std::vector<iaat_problem>>> taken;  // output base, GEMMs
       while (!queue.empty()) {
         Req& R = reqs[queue.front() - 1];
         if (n > 0 && n + R.n > cfg.max_batch_gemms) break;
@@ -178,18 +190,9 @@ struct iaat_server {
         R.t_launch = t;
         L.tickets.push_back(queue.front());
         L.first.push_back(n);
-        float* out = arena + off / sizeof(float);
-        for (int32_t i = 0; i < R.n; ++i) {
-          iaat_problem p = R.g[i];
-          const float* c0 = p.C;
-          p.C = out;
-          if (p.beta != 0.0f && p.m > 0 && p.n > 0)
-            L.cp_host[ncp++] = CopySpan{c0, out, (int64_t)p.ldc * p.n};
-          L.desc_host[n + i] = p;
-          out += out_floats(R.g[i]);
-        }
+        taken.emplace_back(arena + off / sizeof(float), std::move(R.g));
         n += R.n;
-        std::vector<iaat_problem>().swap(R.g);
+        queued_gemms -= R.n;
         queue.pop_front();
       }
       if (n == 0) break;  // the head request waits for arena space
@@ -198,16 +201,30 @@ struct iaat_server {
       ++launches;
       any = true;
       lk.unlock();
-      hipError_t e = hipMemcpyAsync(L.desc_dev, L.desc_host, n * sizeof(iaat_problem),
+      // outside the lock: descriptors with their outputs in the arena, and
+      // the copies that seed outputs from C0 when beta != 0
+      int64_t ncp = 0, d = 0;
+      for (auto& tk : taken) {
+        float* out = tk.first;
+        for (const iaat_problem& g : tk.second) {
+          iaat_problem p = g;
+          p.C = out;
+          if (p.beta != 0.0f && p.m > 0 && p.n > 0) L.cp_host[ncp++] = CopySpan{g.C, out, (int64_t)p.ldc * p.n};
+          L.desc_host[d++] = p;
+          out += out_floats(g);
+        }
+      }
+      taken.clear();
+      // descriptors then copy spans, contiguous in the slot's staging buffer
+      const size_t dbytes = (size_t)n * sizeof(iaat_problem);
+      if (ncp > 0) memmove(L.stage_host + dbytes, L.cp_host, (size_t)ncp * sizeof(CopySpan));
+      hipError_t e = hipMemcpyAsync(L.stage_dev, L.stage_host, dbytes + (size_t)ncp * sizeof(CopySpan),
                                     hipMemcpyHostToDevice, L.stream);
       if (e == hipSuccess && ncp > 0)
-        e = hipMemcpyAsync(L.cp_dev, L.cp_host, ncp * sizeof(CopySpan), hipMemcpyHostToDevice,
-                           L.stream);
-      if (e == hipSuccess && ncp > 0)
-        e = launch_copy_spans(L.cp_dev, ncp, (int)std::min<int64_t>(ncp, 4LL * ctx->num_cu), L.stream);
-      if (e == hipSuccess) e = launch_batch(ctx, L.desc_dev, n, cfg.prec, L.st_dev, L.stream);
+        e = launch_copy_spans((const CopySpan*)(L.stage_dev + dbytes), ncp,
+                              (int)std::min<int64_t>(ncp, 4LL * ctx->num_cu), L.stream);
       if (e == hipSuccess)
-        e = hipMemcpyAsync(L.st_host, L.st_dev, n * sizeof(int32_t), hipMemcpyDeviceToHost, L.stream);
+        e = launch_batch(ctx, (const iaat_problem*)L.stage_dev, n, cfg.prec, nullptr, L.stream);
       if (e == hipSuccess) e = hipEventRecord(L.ev, L.stream);
       lk.lock();
       if (e != hipSuccess) {  // the requests fail; the slot is reusable once the stream drains
@@ -231,7 +248,7 @@ struct iaat_server {
       const bool b = admit(lk);
       if (stopping && queue.empty() && in_flight == 0) break;
       if (a || b) continue;
-      if (in_flight > 0) {  // poll the events again shortly
+      if (in_flight > 0 || !queue.empty()) {  // poll the events / batching window again shortly
         lk.unlock();
         std::this_thread::yield();
         lk.lock();
@@ -244,12 +261,9 @@ struct iaat_server {
 
 static void free_server(iaat_server* S) {
   for (Launch& L : S->slots) {
-    if (L.desc_host) (void)hipHostFree(L.desc_host);
-    if (L.st_host) (void)hipHostFree(L.st_host);
+    if (L.stage_host) (void)hipHostFree(L.stage_host);
     if (L.cp_host) (void)hipHostFree(L.cp_host);
-    if (L.desc_dev) (void)hipFree(L.desc_dev);
-    if (L.st_dev) (void)hipFree(L.st_dev);
-    if (L.cp_dev) (void)hipFree(L.cp_dev);
+    if (L.stage_dev) (void)hipFree(L.stage_dev);
     if (L.ev) (void)hipEventDestroy(L.ev);
   }
   for (hipStream_t s : S->streams) (void)hipStreamDestroy(s);
@@ -284,13 +298,12 @@ int iaat_serve_start(iaat_ctx_t ctx, const iaat_serve_cfg* cfg, iaat_server_t* o
   for (size_t i = 0; i < S->slots.size() && e == hipSuccess; ++i) {
     Launch& L = S->slots[i];
     L.stream = S->streams[i % S->streams.size()];
-    if (e == hipSuccess) e = hipHostMalloc((void**)&L.desc_host, mb * sizeof(iaat_problem), 0);
-    if (e == hipSuccess) e = hipHostMalloc((void**)&L.st_host, mb * sizeof(int32_t), 0);
+    const size_t sbytes = mb * (sizeof(iaat_problem) + sizeof(CopySpan));
+    if (e == hipSuccess) e = hipHostMalloc((void**)&L.stage_host, sbytes, 0);
     if (e == hipSuccess) e = hipHostMalloc((void**)&L.cp_host, mb * sizeof(CopySpan), 0);
-    if (e == hipSuccess) e = hipMalloc(&L.desc_dev, mb * sizeof(iaat_problem));
-    if (e == hipSuccess) e = hipMalloc(&L.st_dev, mb * sizeof(int32_t));
-    if (e == hipSuccess) e = hipMalloc(&L.cp_dev, mb * sizeof(CopySpan));
+    if (e == hipSuccess) e = hipMalloc((void**)&L.stage_dev, sbytes);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&L.ev, hipEventDisableTiming);
+    L.desc_host = (iaat_problem*)L.stage_host;
   }
   if (e != hipSuccess) {
     free_server(S);
@@ -302,6 +315,11 @@ int iaat_serve_start(iaat_ctx_t ctx, const iaat_serve_cfg* cfg, iaat_server_t* o
   return IAAT_OK;
 }
 
+// Appends a request; `sizes` (when not NULL) gives the GEMMs' output bytes
+// and flops already checked (the replay validates its pool once).
+static int submit_request(iaat_server_t S, const iaat_problem* gemms, int64_t count, double t_arrival,
+                          int keep_output, uint64_t* ticket, uint64_t bytes, double flops);
+
 int iaat_serve_submit(iaat_server_t S, const iaat_problem* gemms, int64_t count, double t_arrival,
                       int keep_output, uint64_t* ticket) {
   if (!S) return fail(-1, "iaat_serve_submit: server is NULL");
@@ -310,8 +328,8 @@ int iaat_serve_submit(iaat_server_t S, const iaat_problem* gemms, int64_t count,
     return fail(-3, "iaat_serve_submit: %lld GEMMs > max_batch_gemms %d", (long long)count,
                 S->cfg.max_batch_gemms);
   if (!ticket) return fail(-6, "iaat_serve_submit: ticket is NULL");
-  Req R;
-  R.g.assign(gemms, gemms + count);
+  uint64_t bytes = 0;
+  double flops = 0;
   for (int64_t i = 0; i < count; ++i) {
     const iaat_problem& p = gemms[i];
     // the output is arena memory; C names the initial value, read only when beta != 0
@@ -320,12 +338,21 @@ int iaat_serve_submit(iaat_server_t S, const iaat_problem* gemms, int64_t count,
     if (st == 0 && p.beta != 0.0f && p.m > 0 && p.n > 0 && p.C == nullptr) st = -13;
     if (st != 0)
       return fail(-4, "iaat_serve_submit: GEMM %lld: argument %d invalid", (long long)i, -st);
-    R.bytes += (uint64_t)out_floats(p) * sizeof(float);
-    R.flops += 2.0 * p.m * (double)p.n * p.k;
+    bytes += (uint64_t)out_floats(p) * sizeof(float);
+    flops += 2.0 * p.m * (double)p.n * p.k;
   }
-  if (R.bytes > S->cfg.mem_cap_bytes)
+  return submit_request(S, gemms, count, t_arrival, keep_output, ticket, bytes, flops);
+}
+
+static int submit_request(iaat_server_t S, const iaat_problem* gemms, int64_t count, double t_arrival,
+                          int keep_output, uint64_t* ticket, uint64_t bytes, double flops) {
+  if (bytes > S->cfg.mem_cap_bytes)
     return fail(-3, "iaat_serve_submit: outputs of %llu bytes exceed the arena",
-                (unsigned long long)R.bytes);
+                (unsigned long long)bytes);
+  Req R;
+  R.g.assign(gemms, gemms + count);
+  R.bytes = bytes;
+  R.flops = flops;
   R.n = (int32_t)count;
   R.keep = keep_output != 0;
   {
@@ -335,6 +362,7 @@ int iaat_serve_submit(iaat_server_t S, const iaat_problem* gemms, int64_t count,
     S->reqs.push_back(std::move(R));
     *ticket = S->reqs.size();
     S->queue.push_back(*ticket);
+    S->queued_gemms += count;
     S->peak_queue = std::max<int64_t>(S->peak_queue, (int64_t)S->queue.size());
   }
   S->cv_work.notify_one();
@@ -408,6 +436,18 @@ int iaat_serve_replay(iaat_server_t S, int64_t n_req, const double* t_arrival,
   if (n_req < 0) return fail(-2, "iaat_serve_replay: n_req < 0");
   if (n_req > 0 && (!t_arrival || !n_gemms || !pool_idx || !pool || pool_size < 1))
     return fail(-3, "iaat_serve_replay: missing trace arrays");
+  // validate the pool once; per-entry output bytes and flops
+  std::vector<uint64_t> pbytes((size_t)pool_size);
+  std::vector<double> pflops((size_t)pool_size);
+  for (int64_t i = 0; i < pool_size && n_req > 0; ++i) {
+    const iaat_problem& p = pool[i];
+    static const float dummy = 0.0f;
+    int st = validate(p.trans, p.m, p.n, p.k, p.lda, p.ldb, p.ldc, p.alpha, p.A, p.B, &dummy);
+    if (st == 0 && p.beta != 0.0f && p.m > 0 && p.n > 0 && p.C == nullptr) st = -13;
+    if (st != 0) return fail(-5, "iaat_serve_replay: pool entry %lld: argument %d invalid", (long long)i, -st);
+    pbytes[(size_t)i] = (uint64_t)out_floats(p) * sizeof(float);
+    pflops[(size_t)i] = 2.0 * p.m * (double)p.n * p.k;
+  }
   std::vector<uint64_t> tickets((size_t)n_req, 0);
   std::vector<iaat_problem> g;
   const double t_start = S->now();
@@ -421,14 +461,26 @@ int iaat_serve_replay(iaat_server_t S, int64_t n_req, const double* t_arrival,
       else
         std::this_thread::yield();
     }
+    if (n_gemms[r] < 1 || n_gemms[r] > S->cfg.max_batch_gemms) {
+      rc = fail(-4, "iaat_serve_replay: request %lld has %d GEMMs", (long long)r, n_gemms[r]);
+      break;
+    }
     g.resize((size_t)n_gemms[r]);
+    uint64_t bytes = 0;
+    double flops = 0;
     for (int32_t i = 0; i < n_gemms[r]; ++i) {
       const int64_t p = pool_idx[first + i];
-      if (p < 0 || p >= pool_size) return fail(-6, "iaat_serve_replay: pool index %lld", (long long)p);
+      if (p < 0 || p >= pool_size) {
+        rc = fail(-6, "iaat_serve_replay: pool index %lld", (long long)p);
+        break;
+      }
       g[i] = pool[p];
+      bytes += pbytes[(size_t)p];
+      flops += pflops[(size_t)p];
     }
+    if (rc != IAAT_OK) break;
     first += n_gemms[r];
-    rc = iaat_serve_submit(S, g.data(), n_gemms[r], target, 0, &tickets[r]);
+    rc = submit_request(S, g.data(), n_gemms[r], target, 0, &tickets[r], bytes, flops);
   }
   // wait for every submitted request
   std::unique_lock<std::mutex> lk(S->mu);
