@@ -9,7 +9,8 @@ code with it: no kernels, headers, helpers, tables or generators.
 Contents
   gemm_f64.c   FP64 triple-loop GEMM (Section I statement, Table 1 note for the
                layouts) for FP32 inputs, and the same loop with FP64 operands
-               (DGEMM, Table 1 row D), built with gcc into ``_build/liboracle.so``.
+               (DGEMM, Table 1 row D), and the complex loop (CGEMM, row C),
+               built with gcc into ``_build/liboracle.so``.
   quant.py     BF16 / FP16 / FP8-E4M3 rounding from the format definitions,
                the split-BF16 pair, the power-of-two FP8 scale.
   tiler_ref.py A reading of the SGEMM_NN tile algorithm (Section V-A,
@@ -62,6 +63,9 @@ def _load():
             lib.oracle_gemm_f64_d.restype = None
             lib.oracle_dgemm.argtypes = lib.oracle_gemm_f64.argtypes
             lib.oracle_dgemm.restype = None
+            lib.oracle_cgemm.argtypes = [i32, i32, i64, i64, i64, dbl, dbl, vp, i64, vp, i64,
+                                         dbl, dbl, vp, i64, vp, i64]
+            lib.oracle_cgemm.restype = None
             lib.oracle_gemm_batch.argtypes = [i64] + [vp] * 15 + [i32]
             lib.oracle_gemm_batch.restype = dbl
             _lib = lib
@@ -114,6 +118,21 @@ def dgemm(ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C0, ldc):
     if m > 0 and n > 0:
         lib.oracle_dgemm(int(ta), int(tb), m, n, k, float(alpha), _ptr(a), lda, _ptr(b), ldb,
                          float(beta), _ptr(c), ldc, _ptr(out), max(m, 1))
+    return out[:n, :m].T.copy()
+
+
+def cgemm(ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C0, ldc):
+    """CGEMM (Table 1, row C): complex64 operands (numpy arrays of the stored
+    matrices, column-major, flat), complex alpha/beta; complex128 m x n result."""
+    lib = _load()
+    out = np.zeros((max(n, 1), max(m, 1)), dtype=np.complex128)
+    a = None if A is None else np.ascontiguousarray(A, dtype=np.complex64)
+    b = None if B is None else np.ascontiguousarray(B, dtype=np.complex64)
+    c = None if C0 is None else np.ascontiguousarray(C0, dtype=np.complex64)
+    al, be = complex(alpha), complex(beta)
+    if m > 0 and n > 0:
+        lib.oracle_cgemm(int(ta), int(tb), m, n, k, al.real, al.imag, _ptr(a), lda, _ptr(b), ldb,
+                         be.real, be.imag, _ptr(c), ldc, _ptr(out), max(m, 1))
     return out[:n, :m].T.copy()
 
 

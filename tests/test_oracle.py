@@ -253,3 +253,59 @@ def test_dgemm_brute_force_tiny():
             for i in range(m):
                 for j in range(n):
                     assert got[i, j] == sum(a[i + p * m] * b[p + j * k] for p in range(k))
+
+
+# ---- CGEMM (complex): pinned independently
+
+def _crand(rng, shape):
+    return (rng.uniform(-1, 1, shape) + 1j * rng.uniform(-1, 1, shape)).astype(np.complex64)
+
+
+def test_cgemm_identity_and_scalars():
+    rng = np.random.Generator(np.random.PCG64(911))
+    m, n = 6, 4
+    B = _crand(rng, (m, n))
+    C0 = _crand(rng, (m, n))
+    al, be = 1.5 - 0.5j, 0.25 + 2j
+    got = oracle.cgemm(0, 0, m, n, m, al, np.eye(m, dtype=np.complex64).ravel(order="F"), m,
+                       B.ravel(order="F"), m, be, C0.ravel(order="F"), m)
+    exp = al * B.astype(np.complex128) + be * C0.astype(np.complex128)
+    assert np.array_equal(got, exp)
+
+
+def test_cgemm_rank_one_gaussian_integers():
+    rng = np.random.Generator(np.random.PCG64(912))
+    m, n, K = 5, 3, 7
+    x = (rng.integers(-3, 4, m) + 1j * rng.integers(-3, 4, m)).astype(np.complex64)
+    y = (rng.integers(-3, 4, n) + 1j * rng.integers(-3, 4, n)).astype(np.complex64)
+    A = np.outer(x, np.ones(K)).astype(np.complex64)
+    B = np.outer(np.ones(K), y).astype(np.complex64)
+    got = oracle.cgemm(0, 0, m, n, K, 1j, A.ravel(order="F"), m, B.ravel(order="F"), K, 0, None, m)
+    assert np.array_equal(got, 1j * K * np.outer(x.astype(np.complex128), y.astype(np.complex128)))
+
+
+def test_cgemm_quick_return_rules():
+    m, n, k = 2, 3, 4
+    A = np.full(m * k, np.nan, dtype=np.complex64)
+    C0 = (np.arange(m * n) + 1j).astype(np.complex64)
+    got = oracle.cgemm(0, 0, m, n, k, 0, A, m, A, k, 2 - 1j, C0, m)
+    assert np.array_equal(got, (2 - 1j) * C0.astype(np.complex128).reshape(n, m).T)
+    ones = np.ones(m * k, dtype=np.complex64)
+    got = oracle.cgemm(0, 0, m, n, k, 1, ones, m, np.ones(k * n, dtype=np.complex64), k, 0,
+                       np.full(m * n, np.nan, dtype=np.complex64), m)
+    assert np.array_equal(got, np.full((m, n), float(k), dtype=np.complex128))
+
+
+@pytest.mark.parametrize("lay", ["NN", "NT", "TN", "TT"])
+def test_cgemm_against_numpy(lay):
+    rng = np.random.Generator(np.random.PCG64(913))
+    m, n, k = 9, 7, 11
+    Aop, Bop, C0 = _crand(rng, (m, k)), _crand(rng, (k, n)), _crand(rng, (m, n))
+    ta, tb = lay[0] == "T", lay[1] == "T"
+    A = (Aop.T if ta else Aop).ravel(order="F")
+    B = (Bop.T if tb else Bop).ravel(order="F")
+    al, be = 0.5 + 0.25j, -1 + 0.5j
+    got = oracle.cgemm(int(ta), int(tb), m, n, k, al, A, k if ta else m, B, n if tb else k, be,
+                       C0.ravel(order="F"), m)
+    ref = al * (Aop.astype(np.complex128) @ Bop.astype(np.complex128)) + be * C0.astype(np.complex128)
+    assert np.max(np.abs(got - ref)) <= 1e-12
