@@ -178,6 +178,25 @@ def dgemm_leg(iaat, h, dev, stream):
     return res
 
 
+def cgemm_leg(iaat, h, dev, stream):
+    """CGEMM same-size batches (interleaved complex FP32); flops 8MNK (Eq. 2)."""
+    import torch
+    res = {}
+    sp = stream.cuda_stream
+    for (m, n, k, batch) in ((16, 16, 16, 65536), (80, 80, 80, 4096)):
+        g = torch.Generator(device="cpu").manual_seed(m + 2)
+        mk = lambda c: (torch.rand(2 * c, generator=g) * 2 - 1).to(dev)
+        A, B, C = mk(batch * m * k), mk(batch * k * n), mk(batch * m * n)
+        ms = _events_ms(torch, stream, lambda: iaat.iaat_cgemm_strided_batched(
+            h, 0, 0, m, n, k, 1.0, A.data_ptr(), m, m * k, B.data_ptr(), k, k * n, 1.0,
+            C.data_ptr(), m, m * n, batch, sp), 10)
+        byt = 8.0 * batch * (m * k + k * n + 2 * m * n)
+        res["nn%d_x%d" % (m, batch)] = {"us": round(ms * 1e3, 1), "gbs": round(byt / ms / 1e6, 1),
+                                        "hbm_frac": round(byt / ms / 1e6 / HBM_PEAK_GBS, 4),
+                                        "gflops": round(8.0 * batch * m * n * k / ms / 1e6, 1)}
+    return res
+
+
 def precision_leg(iaat, inputs, h, dev, stream):
     """Reduced-precision inputs on the sweep grid (2 problems per shape,
     |x| = 10^U(-3,3)): on-device quantisation and the batched GEMM, per type.
@@ -396,6 +415,7 @@ def main() -> int:
         extra["strided_same_size"] = strided_leg(iaat, ctx.handle, dev, stream)
         extra["ablation_traditional"] = traditional_leg(iaat, ctx.handle, ps, desc, ms, dev, stream)
         extra["dgemm_same_size"] = dgemm_leg(iaat, ctx.handle, dev, stream)
+        extra["cgemm_same_size"] = cgemm_leg(iaat, ctx.handle, dev, stream)
     if not args.no_precision:
         extra["precision"] = precision_leg(iaat, inputs, ctx.handle, dev, stream)
     if not args.no_serve:

@@ -144,6 +144,22 @@ int iaat_dgemm_strided_batched(iaat_ctx_t ctx, int ta, int tb, int64_t m, int64_
                                double* C, int64_t ldc, int64_t stride_c, int64_t batch,
                                iaat_stream_t stream);
 
+/* CGEMM (Table 1, row C): complex single precision.  A, B, C hold
+ * interleaved (re, im) FP32 pairs; lda, ldb, ldc and strides count complex
+ * elements; alpha and beta point to host (re, im) pairs; op(X) = X or X^T
+ * (no conjugation).  Same blocking as DGEMM; each complex product is four
+ * real matrix-core accumulations.  Argument numbers, quick returns (alpha =
+ * 0 + 0i or K = 0: C = beta*C; beta = 0 + 0i: C not read) and NULL rules as
+ * iaat_gemm / iaat_gemm_strided_batched (-7 / -14: alpha / beta NULL). */
+int iaat_cgemm(iaat_ctx_t ctx, int ta, int tb, int64_t m, int64_t n, int64_t k, const float* alpha,
+               const void* A, int64_t lda, const void* B, int64_t ldb, const float* beta, void* C,
+               int64_t ldc, iaat_stream_t stream);
+int iaat_cgemm_strided_batched(iaat_ctx_t ctx, int ta, int tb, int64_t m, int64_t n, int64_t k,
+                               const float* alpha, const void* A, int64_t lda, int64_t stride_a,
+                               const void* B, int64_t ldb, int64_t stride_b, const float* beta,
+                               void* C, int64_t ldc, int64_t stride_c, int64_t batch,
+                               iaat_stream_t stream);
+
 /* ------------------------------------------------- many uneven problems */
 
 /* One problem of a batch: 64 bytes, naturally aligned. */

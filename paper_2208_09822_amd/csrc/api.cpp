@@ -305,6 +305,54 @@ int iaat_dgemm(iaat_ctx_t ctx, int ta, int tb, int64_t m, int64_t n, int64_t k, 
   return (rc < 0 && rc > -19) ? back[-rc] : rc;
 }
 
+int iaat_cgemm_strided_batched(iaat_ctx_t ctx, int ta, int tb, int64_t m, int64_t n, int64_t k,
+                               const float* alpha, const void* A, int64_t lda, int64_t stride_a,
+                               const void* B, int64_t ldb, int64_t stride_b, const float* beta,
+                               void* C, int64_t ldc, int64_t stride_c, int64_t batch,
+                               iaat_stream_t stream) {
+  if (!ctx) return fail(-1, "iaat_cgemm: ctx is NULL");
+  if (ta != IAAT_OP_N && ta != IAAT_OP_T) return fail(-2, "iaat_cgemm: ta=%d", ta);
+  if (tb != IAAT_OP_N && tb != IAAT_OP_T) return fail(-3, "iaat_cgemm: tb=%d", tb);
+  if (!alpha) return fail(-7, "iaat_cgemm: alpha is NULL");
+  if (!beta) return fail(-14, "iaat_cgemm: beta is NULL");
+  const int layout = ta | (tb << 1);
+  const bool a0 = alpha[0] == 0.0f && alpha[1] == 0.0f;
+  int st = validate(layout, m, n, k, lda, ldb, ldc, a0 ? 0.0f : 1.0f, A, B, C);
+  static const int remap[15] = {0, 0, -2, -3, -4, -5, -6, 0, -8, -9, -11, -12, 0, -15, -16};
+  if (st != 0) {
+    st = remap[-st];
+    return fail(st, "iaat_cgemm: invalid argument %d", -st);
+  }
+  if (batch < 0) return fail(-18, "iaat_cgemm: batch=%lld", (long long)batch);
+  if (stride_a < 0) return fail(-10, "iaat_cgemm: stride_a=%lld", (long long)stride_a);
+  if (stride_b < 0) return fail(-13, "iaat_cgemm: stride_b=%lld", (long long)stride_b);
+  if (batch > 1 && m > 0 && n > 0 && stride_c < ldc * n)
+    return fail(-17, "iaat_cgemm: stride_c=%lld < ldc*n (outputs overlap)", (long long)stride_c);
+  if (m == 0 || n == 0 || batch == 0) return IAAT_OK;
+  if (m > 0x7fff0000LL || n > 0x7fff0000LL)
+    return fail(IAAT_ERR_UNSUPPORTED, "iaat_cgemm: %lld x %lld is too large", (long long)m, (long long)n);
+  DeviceGuard g(ctx->device);
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e;
+  if (a0 || k == 0) {
+    e = launch_cscale((float*)C, (int)m, (int)n, ldc, beta[0], beta[1], stride_c, batch, s);
+  } else {
+    CProb P{(const float*)A, (const float*)B, (float*)C, (int)m, (int)n, (int)k, (int)lda, (int)ldb,
+            (int)ldc, alpha[0], alpha[1], beta[0], beta[1]};
+    e = launch_cgemm(P, layout, stride_a, stride_b, stride_c, batch, s);
+  }
+  return e == hipSuccess ? IAAT_OK : hip_fail(e, "iaat_cgemm: launch");
+}
+
+int iaat_cgemm(iaat_ctx_t ctx, int ta, int tb, int64_t m, int64_t n, int64_t k, const float* alpha,
+               const void* A, int64_t lda, const void* B, int64_t ldb, const float* beta, void* C,
+               int64_t ldc, iaat_stream_t stream) {
+  const int rc = iaat_cgemm_strided_batched(ctx, ta, tb, m, n, k, alpha, A, lda, 0, B, ldb, 0, beta,
+                                            C, ldc, 0, 1, stream);
+  static const int back[19] = {0, -1, -2, -3, -4, -5, -6, -7, -8, -9, 0, -10, -11, 0, -12, -13, -14, 0, 0};
+  return (rc < 0 && rc > -19) ? back[-rc] : rc;
+}
+
 struct iaat_tradplan {
   iaat_ctx* ctx = nullptr;
   TradProb* probs = nullptr;

@@ -61,6 +61,19 @@ hipError_t launch_dgemm(const DProb& P, int layout, int64_t sa, int64_t sb, int6
 hipError_t launch_dscale(double* C, int m, int n, int64_t ldc, double beta, int64_t sc, int64_t batch,
                          hipStream_t stream);
 
+// CGEMM (cgemm.hip): interleaved complex FP32, complex scalars.
+struct CProb {
+  const float* A;  // (re, im) pairs
+  const float* B;
+  float* C;
+  int m, n, k, lda, ldb, ldc;  // in complex elements
+  float alpha_re, alpha_im, beta_re, beta_im;
+};
+hipError_t launch_cgemm(const CProb& P, int layout, int64_t sa, int64_t sb, int64_t sc, int64_t batch,
+                        hipStream_t stream);
+hipError_t launch_cscale(float* C, int m, int n, int64_t ldc, float beta_re, float beta_im, int64_t sc,
+                         int64_t batch, hipStream_t stream);
+
 // Traditional pack + uniform-tile scheme (traditional.hip), for ablation.
 struct TradProb {
   const float* A;

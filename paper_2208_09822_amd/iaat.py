@@ -113,6 +113,10 @@ def lib():
                 "iaat_vbplan_create": (i32, [vp, vp, i64, i32, vp, ctypes.POINTER(vp)]),
                 "iaat_quantize_batch": (i32, [vp, i32, vp, i64, vp]),
                 "iaat_trad_create": (i32, [vp, vp, i64, ctypes.POINTER(vp)]),
+                "iaat_cgemm": (i32, [vp, i32, i32, i64, i64, i64, vp, vp, i64, vp, i64, vp, vp, i64,
+                                     vp]),
+                "iaat_cgemm_strided_batched": (i32, [vp, i32, i32, i64, i64, i64, vp, vp, i64, i64,
+                                                     vp, i64, i64, vp, vp, i64, i64, i64, vp]),
                 "iaat_dgemm": (i32, [vp, i32, i32, i64, i64, i64, ctypes.c_double, vp, i64, vp, i64,
                                      ctypes.c_double, vp, i64, vp]),
                 "iaat_dgemm_strided_batched": (i32, [vp, i32, i32, i64, i64, i64, ctypes.c_double,
@@ -210,6 +214,23 @@ def iaat_dgemm_strided_batched(ctx, ta, tb, m, n, k, alpha, A, lda, stride_a, B,
     _check(lib().iaat_dgemm_strided_batched(ctx, ta, tb, m, n, k, alpha, A or None, lda, stride_a,
                                             B or None, ldb, stride_b, beta, C or None, ldc,
                                             stride_c, batch, stream or None))
+
+
+def _cscalar(x):
+    x = complex(x)
+    return (ctypes.c_float * 2)(x.real, x.imag)
+
+
+def iaat_cgemm(ctx, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, stream=0) -> None:
+    _check(lib().iaat_cgemm(ctx, ta, tb, m, n, k, _cscalar(alpha), A or None, lda, B or None, ldb,
+                            _cscalar(beta), C or None, ldc, stream or None))
+
+
+def iaat_cgemm_strided_batched(ctx, ta, tb, m, n, k, alpha, A, lda, stride_a, B, ldb, stride_b,
+                               beta, C, ldc, stride_c, batch, stream=0) -> None:
+    _check(lib().iaat_cgemm_strided_batched(ctx, ta, tb, m, n, k, _cscalar(alpha), A or None, lda,
+                                            stride_a, B or None, ldb, stride_b, _cscalar(beta),
+                                            C or None, ldc, stride_c, batch, stream or None))
 
 
 def iaat_trad_create(ctx, probs_host: np.ndarray) -> int:

@@ -162,3 +162,8 @@ def test_library_has_no_unresolved_internal_symbols():
 def test_dgemm_null_context():
     lib = iaat.lib()
     assert lib.iaat_dgemm(None, 0, 0, 4, 4, 4, 1.0, None, 4, None, 4, 0.0, None, 4, None) == -1
+
+
+def test_cgemm_null_context():
+    lib = iaat.lib()
+    assert lib.iaat_cgemm(None, 0, 0, 4, 4, 4, None, None, 4, None, 4, None, None, 4, None) == -1
