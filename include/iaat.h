@@ -180,10 +180,12 @@ typedef struct iaat_problem {
  * -9 lda, -10 B, -11 ldb, -13 C, -14 ldc).  An invalid problem is skipped;
  * the others are computed. */
 
-/* Computes every problem of a batch in one persistent kernel launch on
- * `stream`.  The descriptors are already in device
- * memory (`probs_dev`, count entries); validation, tile-plan lookup and the
- * work queue all run on the device, so the host does O(1) work.
+/* Computes every problem of a batch in one batched launch on `stream` (a
+ * staging kernel whose work-groups each take windows of 16 problems, plus a
+ * companion kernel for problems too large to stage).  The descriptors are
+ * already in device memory (`probs_dev`, count entries); validation,
+ * tile-plan lookup and batching all run on the device, so the host does
+ * O(1) work.
  *   count >= 0 (arg 3); prec one of IAAT_PREC_* (arg 4); status: NULL or a
  *   device array of count int32 (arg 5).
  * Problems must not write overlapping C.  FP32 results are bitwise identical

@@ -1,8 +1,9 @@
 // Device entry points of libiaat: the per-call kernel (one problem, one
-// work-group per block of its tile plan), the persistent batched kernels
-// (a producer wavefront stages batches of problems in LDS while consumer
-// wavefronts run their kernel executing plans; problems too large to stage
-// go to a direct kernel), and the quick-return scaling kernel.
+// work-group per block of its tile plan), its same-size strided form, the
+// batched kernels (work-groups stage batches of problems in LDS and run
+// their kernel executing plans from there; problems too large to stage go
+// to a direct kernel), the quick-return scaling kernels and the span copy
+// used by the serving loop.
 #include <hip/hip_runtime.h>
 
 #include "iaat_internal.h"
@@ -127,7 +128,7 @@ __global__ __launch_bounds__(64) void scale_strided_kernel(float* C, int m, int 
 }
 
 // ---------------------------------------------------------------------------
-// Batched path: one work-group of four wavefronts per problem.
+// Batched path.
 
 // Kernel family parameters, indexed by kid.
 __constant__ int kKidFam[IAAT_NUM_KIDS] = {
