@@ -268,6 +268,73 @@ def serve_leg(iaat, inputs, h, dev, seconds):
     return res
 
 
+def sweep(iaat, inputs, dev, per_shape, out_path):
+    """The plain-method sweep: for every (layout, M, N, K) of the grid, the
+    same `per_shape` problems one iaat_gemm call each and as one batched
+    launch (ld = stored rows, U[-1,1], alpha = beta = 1)."""
+    import numpy as np
+    import torch
+    shapes = inputs.sweep_shapes()
+    ps = inputs.sweep_problems(per_shape=per_shape)
+    buf = torch.from_numpy(ps.buf).to(dev)
+    base = buf.data_ptr()
+    stream = torch.cuda.current_stream(dev)
+    sp = stream.cuda_stream
+    ctx = iaat.Context(0)
+    from paper_2208_09822_amd import autotune
+    autotune.apply(ctx.handle)
+    desc = torch.from_numpy(iaat.descriptors(ps, base).view(np.uint8)).to(dev)
+    L = iaat.lib()
+    ao = (base + 4 * ps.a_off).tolist(); bo = (base + 4 * ps.b_off).tolist()
+    co = (base + 4 * ps.c_off).tolist()
+    rows = []
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.time()
+    for si, (lay, m, n, k) in enumerate(shapes):
+        q0 = si * per_shape
+        t = inputs.LAYOUT_BITS[lay]
+        lda, ldb = int(ps.lda[q0]), int(ps.ldb[q0])
+
+        def calls():
+            for q in range(q0, q0 + per_shape):
+                L.iaat_gemm(ctx.handle, t & 1, t >> 1, m, n, k, 1.0, ao[q], lda, bo[q], ldb, 1.0,
+                            co[q], m, sp)
+        calls()
+        a.record(stream)
+        calls()
+        b.record(stream)
+        b.synchronize()
+        ms_pc = a.elapsed_time(b)
+        dptr = desc.data_ptr() + 64 * q0
+        iaat.iaat_gemm_vbatched_device(ctx.handle, dptr, per_shape, stream=sp)
+        a.record(stream)
+        iaat.iaat_gemm_vbatched_device(ctx.handle, dptr, per_shape, stream=sp)
+        b.record(stream)
+        b.synchronize()
+        ms_b = a.elapsed_time(b)
+        fl = 2.0 * m * n * k * per_shape
+        rows.append((lay, m, n, k, ms_pc * 1e3 / per_shape, fl / ms_pc / 1e6, ms_b * 1e3, fl / ms_b / 1e6))
+        if si % 2000 == 0:
+            print("[sweep] %d/%d shapes, %.0fs" % (si, len(shapes), time.time() - t0), file=sys.stderr,
+                  flush=True)
+    ctx.close()
+    os.makedirs(os.path.dirname(os.path.abspath(out_path)), exist_ok=True)
+    with open(out_path, "w") as f:
+        f.write("layout,m,n,k,percall_us,percall_gflops,batched_us,batched_gflops\n")
+        for r in rows:
+            f.write("%s,%d,%d,%d,%.3f,%.3f,%.3f,%.3f\n" % r)
+    summ = {}
+    for lay in ("NN", "NT", "TN", "TT"):
+        rr = np.array([r[4:] for r in rows if r[0] == lay])
+        summ[lay] = {"shapes": int(rr.shape[0]), "percall_us_median": round(float(np.median(rr[:, 0])), 2),
+                     "percall_gflops_median": round(float(np.median(rr[:, 1])), 2),
+                     "percall_gflops_max": round(float(np.max(rr[:, 1])), 1),
+                     "batched_gflops_median": round(float(np.median(rr[:, 3])), 1),
+                     "batched_gflops_max": round(float(np.max(rr[:, 3])), 1)}
+    print(json.dumps({"sweep": summ, "per_shape": per_shape, "csv": out_path}), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -284,6 +351,11 @@ def main() -> int:
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=1.0,
                     help="length of each open-loop serving trace (seconds)")
+    ap.add_argument("--sweep", action="store_true",
+                    help="only the shape sweep: every grid shape, one call per problem vs one "
+                         "batched launch; per-shape CSV to --sweep-out, summary JSON to stdout")
+    ap.add_argument("--sweep-per-shape", type=int, default=16)
+    ap.add_argument("--sweep-out", default="gpurun_out/sweep.csv")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -306,6 +378,9 @@ def main() -> int:
         torch.cuda.synchronize()
         print(json.dumps({"calibrate_copy_bytes": 1 << 30, "launches": 3}))
         return 0
+
+    if args.sweep:
+        return sweep(iaat, inputs, dev, args.sweep_per_shape, args.sweep_out)
 
     if args.profile:
         args.steps, args.warmup = 5, 1
