@@ -312,6 +312,8 @@ typedef struct iaat_serve_stats {
     double gflops;                /* 2MNK of done requests / (last t_done - first t_arrival) */
     uint64_t peak_admitted_bytes; /* most arena bytes held at once */
     int64_t peak_queue_depth;     /* most requests waiting for admission */
+    double p99_submit_lag;        /* seconds a request was submitted after its t_arrival
+                                     (load-generator lag, part of the latency) */
 } iaat_serve_stats;
 
 /* Starts a server on the context's device (allocates the arena, streams,

@@ -30,7 +30,7 @@ constexpr int64_t kOutAlign = 64;  // floats: each GEMM's output starts 256-byte
 
 struct Req {
   std::vector<iaat_problem> g;  // dropped once launched
-  double t_arrival = 0, t_launch = -1, t_done = -1;
+  double t_arrival = 0, t_submit = 0, t_launch = -1, t_done = -1;
   uint64_t bytes = 0, arena_off = UINT64_MAX;
   double flops = 0;
   int32_t n = 0;
@@ -79,7 +79,7 @@ struct iaat_server {
   std::chrono::steady_clock::time_point t0;
   uint64_t launches = 0, done = 0, failed = 0, gemms_done = 0;
   double flops_done = 0, first_arrival = INFINITY, last_done = 0;
-  std::vector<double> lat;
+  std::vector<double> lat, lag;
 
   double now() const {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -133,6 +133,7 @@ struct iaat_server {
     first_arrival = std::min(first_arrival, R.t_arrival);
     last_done = std::max(last_done, t);
     lat.push_back(t - R.t_arrival);
+    lag.push_back(R.t_submit - R.t_arrival);
     if (!R.keep) release(R.arena_off, R.bytes);
   }
 
@@ -358,7 +359,8 @@ static int submit_request(iaat_server_t S, const iaat_problem* gemms, int64_t co
   {
     std::lock_guard<std::mutex> lk(S->mu);
     if (S->stopping) return fail(IAAT_ERR_UNSUPPORTED, "iaat_serve_submit: server is stopping");
-    R.t_arrival = t_arrival < 0 ? S->now() : t_arrival;
+    R.t_submit = S->now();
+    R.t_arrival = t_arrival < 0 ? R.t_submit : t_arrival;
     S->reqs.push_back(std::move(R));
     *ticket = S->reqs.size();
     S->queue.push_back(*ticket);
@@ -423,6 +425,12 @@ int iaat_serve_stats_get(iaat_server_t S, iaat_serve_stats* out) {
     out->max_latency = *std::max_element(v.begin(), v.end());
     const double span = S->last_done - S->first_arrival;
     out->gflops = span > 0 ? S->flops_done / span / 1e9 : 0.0;
+  }
+  if (!S->lag.empty()) {
+    std::vector<double> v(S->lag);
+    const size_t i = std::min(v.size() - 1, (size_t)(0.99 * (v.size() - 1) + 0.5));
+    std::nth_element(v.begin(), v.begin() + i, v.end());
+    out->p99_submit_lag = v[i];
   }
   out->peak_admitted_bytes = S->peak_held;
   out->peak_queue_depth = S->peak_queue;

@@ -71,7 +71,7 @@ class ServeStats(ctypes.Structure):
                 ("launches", ctypes.c_uint64), ("gemms_done", ctypes.c_uint64),
                 ("p50", ctypes.c_double), ("p99", ctypes.c_double), ("max_latency", ctypes.c_double),
                 ("gflops", ctypes.c_double), ("peak_admitted_bytes", ctypes.c_uint64),
-                ("peak_queue_depth", ctypes.c_int64)]
+                ("peak_queue_depth", ctypes.c_int64), ("p99_submit_lag", ctypes.c_double)]
 
 
 IAAT_REQ_QUEUED, IAAT_REQ_ADMITTED, IAAT_REQ_DONE = 0, 1, 3
