@@ -356,7 +356,7 @@ def main() -> int:
                     help="only the shape sweep: every grid shape, one call per problem vs one "
                          "batched launch; per-shape CSV to --sweep-out, summary JSON to stdout")
     ap.add_argument("--sweep-per-shape", type=int, default=16)
-    ap.add_argument("--sweep-out", default="gpurun_out/sweep.csv")
+    ap.add_argument("--sweep-out", default="sweep.csv")
     args = ap.parse_args()
 
     if args.gpus != 1:

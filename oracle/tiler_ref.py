@@ -24,7 +24,8 @@ Readings taken where the algorithm is silent or ambiguous:
   * CompareLessMemops: smaller S wins; on a tie fewer blocks, then the
     16-based merge.
 Only the 15 x 15 case is fixed by a number the paper prints; the other
-branches are checked by invariants (exact cover, kernel membership).
+branches are parity unpinned: they are checked by invariants only (exact
+cover, kernel membership, no better than the strip-DP optimum).
 """
 from __future__ import annotations
 
