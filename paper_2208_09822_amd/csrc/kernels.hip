@@ -185,11 +185,12 @@ struct CopyJob {
 };
 
 __shared__ __attribute__((aligned(16))) float g_stage[kStage];
-__shared__ BatchProb g_bprob[kMaxBatch];
-__shared__ uint32_t g_bblk[kMaxBatchBlocks];  // plan block | problem slot << 24
-__shared__ CopyJob g_copy[3 * kMaxBatch];
-__shared__ int g_bhead[4];                    // problems, blocks, copies, more-to-come
-__shared__ __attribute__((aligned(16))) uint32_t g_ring[2][16 * 16];  // descriptor windows read ahead
+// Batch tables, double-buffered: wavefront 0 packs batch i+1 while batch i
+// is computed.
+__shared__ BatchProb g_bprob[2][kMaxBatch];
+__shared__ uint32_t g_bblk[2][kMaxBatchBlocks];  // plan block | problem slot << 24
+__shared__ CopyJob g_copy[2][3 * kMaxBatch];
+__shared__ int g_bhead[2][4];                    // problems, blocks, copies, more-to-come
 
 // Staged size of one problem: A, B and (beta != 0) C spans, each widened to
 // whole 16-byte units around it.
@@ -277,28 +278,6 @@ __device__ __forceinline__ void window_load_plan(DescWindow& W, const PlanEntry*
   W.b3 = e->blk[3];
 }
 
-// Window read-ahead through LDS: one memory-to-LDS load brings a window's
-// 16 descriptors (lane L: bytes 16L..16L+15 of the 1 KB); lanes past the
-// end of the array load nothing.
-__device__ __forceinline__ void ring_load(uint32_t* slot, const VbArgs& a, int64_t base) {
-  const int L = lane();
-  if (base + (L >> 2) < a.count)
-    copy16_lds((const float*)(reinterpret_cast<const char*>(a.probs + base) + 16 * L),
-               (lds_f*)(__attribute__((address_space(3))) uint32_t*)slot);
-}
-
-__device__ __forceinline__ void window_from_ring(DescWindow& W, const uint32_t* slot) {
-  const uint4* src = reinterpret_cast<const uint4*>(slot + 16 * (lane() & (kWin - 1)));
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const uint4 v = src[i];
-    W.w[4 * i] = v.x;
-    W.w[4 * i + 1] = v.y;
-    W.w[4 * i + 2] = v.z;
-    W.w[4 * i + 3] = v.w;
-  }
-}
-
 // The problem held by this lane / by lane `l` of a window.
 __device__ __forceinline__ Prob lane_prob(const DescWindow& W) {
   const uint64_t A = ((uint64_t)W.w[1] << 32) | W.w[0];
@@ -364,28 +343,23 @@ __device__ __forceinline__ int scan16(int v) {
 // lane) plus prefix sums, then every taken lane writes its own table
 // entries; so the cost per batch does not grow with the number of problems.
 __device__ __forceinline__ void pack_batch(const VbArgs& a, int64_t G, int64_t nwin, int64_t& win,
-                                           int& i, DescWindow& W0, DescWindow& W1, int& r,
-                                           LaneProb& LP) {
+                                           int& i, DescWindow& W0, DescWindow& W1, LaneProb& LP,
+                                           int tb) {
   const int l = lane();
   int used = 0, np = 0, nb = 0, nc = 0;
   bool more = true;
   for (;;) {
-    if (i == kWin) {  // window done: W1 (words and plan head) was read one window ahead
+    if (i == kWin) {  // window done: W1's words were read one window ahead
       win += G;
       if (win >= nwin) {
         more = false;
         break;
       }
+      window_load_plan(W1, a.table);
       W0 = W1;
       i = 0;
-      ++r;
       LP = classify(W0, l < kWin && win * kWin + l < a.count);
-      if (win + G < nwin) {
-        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // the ring slot has landed
-        window_from_ring(W1, g_ring[(r + 1) & 1]);
-        window_load_plan(W1, a.table);
-        if (win + 2 * G < nwin) ring_load(g_ring[r & 1], a, (win + 2 * G) * kWin);
-      }
+      if (win + G < nwin) window_load(W1, a, (win + G) * kWin);
     }
     // candidates: lanes >= i that are staged
     const bool cand = l >= i && l < kWin && LP.cls == CLS_STAGE;
@@ -413,7 +387,7 @@ __device__ __forceinline__ void pack_batch(const VbArgs& a, int64_t G, int64_t n
       const int off = used + c_need - LP.need;  // staging offset of this problem
       const Prob P = lane_prob(W0);
       const PcGeom& g = LP.g;
-      BatchProb& bp = g_bprob[slot];
+      BatchProb& bp = g_bprob[tb][slot];
       bp.C = P.C;
       bp.la = off + g.a_sh;
       bp.lb = off + 4 * g.a_n4 + g.b_sh;
@@ -427,18 +401,20 @@ __device__ __forceinline__ void pack_batch(const VbArgs& a, int64_t G, int64_t n
       bp.alpha = P.alpha;
       bp.beta = P.beta;
       bp.trans = (int)W0.w[6];
-      g_copy[3 * slot] = CopyJob{P.A - g.a_sh, off, g.a_n4};
-      g_copy[3 * slot + 1] = CopyJob{P.B - g.b_sh, off + 4 * g.a_n4, g.b_n4};
-      g_copy[3 * slot + 2] = CopyJob{P.C - g.c_sh, off + 4 * (g.a_n4 + g.b_n4), g.c_n4};
+      CopyJob* cj = g_copy[tb] + 3 * slot;
+      cj[0] = CopyJob{P.A - g.a_sh, off, g.a_n4};
+      cj[1] = CopyJob{P.B - g.b_sh, off + 4 * g.a_n4, g.b_n4};
+      cj[2] = CopyJob{P.C - g.c_sh, off + 4 * (g.a_n4 + g.b_n4), g.c_n4};
       const int b0 = nb + c_blk - LP.nbp;
       const uint32_t tag = (uint32_t)slot << 24;
-      if (LP.nbp > 0) g_bblk[b0] = W0.b0 | tag;
-      if (LP.nbp > 1) g_bblk[b0 + 1] = W0.b1 | tag;
-      if (LP.nbp > 2) g_bblk[b0 + 2] = W0.b2 | tag;
-      if (LP.nbp > 3) g_bblk[b0 + 3] = W0.b3 | tag;
+      uint32_t* bb = g_bblk[tb] + b0;
+      if (LP.nbp > 0) bb[0] = W0.b0 | tag;
+      if (LP.nbp > 1) bb[1] = W0.b1 | tag;
+      if (LP.nbp > 2) bb[2] = W0.b2 | tag;
+      if (LP.nbp > 3) bb[3] = W0.b3 | tag;
       if (LP.nbp > 4) {
         const PlanEntry* e = a.table + plan_index((int)W0.w[6] & 3, P.m, P.n);
-        for (int b = 4; b < LP.nbp; ++b) g_bblk[b0 + b] = e->blk[b] | tag;
+        for (int b = 4; b < LP.nbp; ++b) bb[b] = e->blk[b] | tag;
       }
     }
     // totals of the taken lanes (lane end-1's prefix values; 0 if none)
@@ -454,10 +430,10 @@ __device__ __forceinline__ void pack_batch(const VbArgs& a, int64_t G, int64_t n
     if (end < kWin) break;  // a problem did not fit: this batch is full
   }
   if (l == 0) {
-    g_bhead[0] = np;
-    g_bhead[1] = nb;
-    g_bhead[2] = nc;
-    g_bhead[3] = more ? 1 : 0;
+    g_bhead[tb][0] = np;
+    g_bhead[tb][1] = nb;
+    g_bhead[tb][2] = nc;
+    g_bhead[tb][3] = more ? 1 : 0;
   }
 }
 
@@ -470,32 +446,32 @@ void vbatched_f32_kernel(VbArgs a) {
   if (win >= nwin) return;
   DescWindow W0, W1;
   LaneProb LP{};
-  int r = 0;  // windows advanced so far
   int i = 0;
   if (w == 0) {
     window_load(W0, a, win * kWin);
     window_load_plan(W0, a.table);
-    if (win + G < nwin) {
-      window_load(W1, a, (win + G) * kWin);
-      window_load_plan(W1, a.table);
-    }
-    if (win + 2 * G < nwin) ring_load(g_ring[0], a, (win + 2 * G) * kWin);
+    if (win + G < nwin) window_load(W1, a, (win + G) * kWin);
     LP = classify(W0, lane() < kWin && win * kWin + lane() < a.count);
+    pack_batch(a, G, nwin, win, i, W0, W1, LP, 0);
   }
   lds_f* stage = (lds_f*)g_stage;
-  for (;;) {
-    if (w == 0) pack_batch(a, G, nwin, win, i, W0, W1, r, LP);
-    __syncthreads();  // batch tables visible
-    const int np = __builtin_amdgcn_readfirstlane(g_bhead[0]);
-    const int nb = __builtin_amdgcn_readfirstlane(g_bhead[1]);
-    const int nc = __builtin_amdgcn_readfirstlane(g_bhead[2]);
-    const int more = __builtin_amdgcn_readfirstlane(g_bhead[3]);
+  __syncthreads();  // batch 0's tables
+  // Iteration t: every wavefront issues its share of batch t's copies; one
+  // wait; wavefronts 1..7 compute batch t from LDS while wavefront 0 packs
+  // batch t+1 into the other table set (its own copies have landed, so its
+  // descriptor reads never wait behind them); a barrier closes the
+  // iteration because the staging buffer is refilled.
+  for (int t = 0;; t ^= 1) {
+    const int np = uni(g_bhead[t][0]);
+    const int nb = uni(g_bhead[t][1]);
+    const int nc = uni(g_bhead[t][2]);
+    const int more = uni(g_bhead[t][3]);
     if (np > 0) {
       // Copies: job c is cut into 64-unit chunks (one memory-to-LDS load
       // instruction each); chunks are numbered across jobs and chunk q goes
       // to wavefront q mod 8.  Lane c holds job c's entry (one LDS read).
       CopyJob my{};
-      if (lane() < nc) my = g_copy[lane()];
+      if (lane() < nc) my = g_copy[t][lane()];
       const uint64_t src_v = (uint64_t)my.src;
       int qbase = 0;
       for (int c = 0; c < nc; ++c) {
@@ -506,19 +482,25 @@ void vbatched_f32_kernel(VbArgs a) {
           const float* g16 = (const float*)su;
           lds_f* dst = stage + rdl(my.dst, c);
           for (int ch = (w - qbase) & (kWaves - 1); ch < nch; ch += kWaves) {
-            const int t = 64 * ch + lane();
-            if (t < n4) copy16_lds(g16 + 4 * t, dst + 256 * ch);
+            const int u = 64 * ch + lane();
+            if (u < n4) copy16_lds(g16 + 4 * u, dst + 256 * ch);
           }
         }
         qbase += nch;
       }
-      staged_barrier();
-      // Blocks w, w + 8, ...: lane t holds block w + 8t.
-      const int myb = w + kWaves * lane();
-      const uint32_t e_v = myb < nb ? g_bblk[myb] : 0u;
-      for (int t = 0; w + kWaves * t < nb; ++t) {
-        const uint32_t e = rdl(e_v, t);
-        const BatchProb& bp = g_bprob[e >> 24];
+    }
+    staged_barrier();  // batch t has landed
+    if (w == 0) {
+      if (more) pack_batch(a, G, nwin, win, i, W0, W1, LP, t ^ 1);
+    } else if (np > 0) {
+      // blocks c, c + 7, ... on compute wavefront c = w - 1: lane u holds block c + 7u
+      constexpr int kCompute = kWaves - 1;
+      const int c0 = w - 1;
+      const int myb = c0 + kCompute * lane();
+      const uint32_t e_v = myb < nb ? g_bblk[t][myb] : 0u;
+      for (int u = 0; c0 + kCompute * u < nb; ++u) {
+        const uint32_t e = rdl(e_v, u);
+        const BatchProb& bp = g_bprob[t][e >> 24];
         const int lc = uni(bp.lc);
         const LdsProb L{stage + uni(bp.la), stage + uni(bp.lb), lc >= 0 ? stage + lc : nullptr,
                         (float*)unip(bp.C), uni(bp.m), uni(bp.n), uni(bp.k), uni(bp.lda),
@@ -534,7 +516,7 @@ void vbatched_f32_kernel(VbArgs a) {
       }
     }
     if (!more) break;
-    __syncthreads();  // the buffer and the batch tables are refilled next
+    __syncthreads();  // batch t computed (buffer free); batch t+1's tables visible
   }
 }
 
