@@ -59,3 +59,28 @@ def test_plan_set_validation_and_save_roundtrip(tmp_path):
     with iaat.Context(0, path) as c2:
         got = [(b[0], b[1], b[4]) for b in iaat.iaat_plan_query(c2.handle, 0, 40, 40)]
         assert got == blocks
+
+
+def test_full_batch_in_the_benchmarked_configuration():
+    """The uneven 65,536-problem batch exactly as bench.py times it (autotuned
+    table, graph-replayed batched launch): integer inputs bit-exact on every
+    problem, uniform inputs on a sample of 4,096 problems."""
+    with iaat.Context(0) as c:
+        autotune.apply(c.handle)
+        s = torch.cuda.current_stream(DEV).cuda_stream
+        for integer in (True, False):
+            ps = inputs.uneven_batch(65536, integer=integer)
+            buf = torch.from_numpy(ps.buf).to(DEV)
+            d = torch.from_numpy(iaat.descriptors(ps, buf.data_ptr()).view(np.uint8)).to(DEV)
+            plan = iaat.iaat_vbplan_create(c.handle, d.data_ptr(), ps.count)
+            try:
+                iaat.iaat_vbplan_launch(plan, s)
+                torch.cuda.synchronize(DEV)
+            finally:
+                iaat.iaat_vbplan_destroy(plan)
+            out = buf.cpu().numpy()
+            sel = None if integer else np.random.Generator(np.random.PCG64(5)).choice(
+                ps.count, 4096, replace=False)
+            ref = oracle_all(ps, select=sel)
+            for q, r in ref.items():
+                check_problem(ps, out, q, r, exact=integer)
