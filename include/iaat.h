@@ -243,7 +243,12 @@ int iaat_quantize_batch(iaat_ctx_t ctx, int prec, const iaat_qjob* jobs_dev, int
  * scalars) between replays; its address and `count` are fixed.
  * iaat_vbplan_create allocates and synchronises the device; launch does
  * neither.
- * create errors: -1 ctx, -2 probs_dev, -3 count, -4 prec, -6 out. */
+ * create errors: -1 ctx, -2 probs_dev, -3 count, -4 prec, -6 out.
+ * An FP32 plan hands the 16-problem windows out to work-groups dynamically
+ * from a counter the plan owns (cleared by a kernel at the start of each
+ * replay), so replays of ONE plan must not overlap: launch them on one
+ * stream, or wait between them.
+ */
 int iaat_vbplan_create(iaat_ctx_t ctx, const iaat_problem* probs_dev, int64_t count, int prec,
                        int32_t* status, iaat_vbplan_t* out);
 int iaat_vbplan_launch(iaat_vbplan_t plan, iaat_stream_t stream);

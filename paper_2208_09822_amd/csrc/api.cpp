@@ -95,8 +95,8 @@ static int max_plan_blocks(iaat_ctx_t ctx, int layout, int64_t m, int64_t n, int
 // The batched launch(es) for one descriptor array: the staged FP32 kernel
 // and its companion, or the reduced-precision kernel.
 hipError_t launch_batch(iaat_ctx_t ctx, const iaat_problem* probs_dev, int64_t count, int prec,
-                        int32_t* status, hipStream_t s) {
-  VbArgs a{probs_dev, count, status, ctx->table_dev};
+                        int32_t* status, hipStream_t s, uint32_t* ticket) {
+  VbArgs a{probs_dev, count, status, ctx->table_dev, ticket};
   if (prec != IAAT_PREC_F32) {
     const int64_t cap = 8LL * ctx->num_cu;  // work-groups of 256 threads, grid-stride over problems
     return launch_vbatched_lowp(a, prec, (int)(count < cap ? count : cap), s);
@@ -500,16 +500,20 @@ int iaat_vbplan_create(iaat_ctx_t ctx, const iaat_problem* probs_dev, int64_t co
   hipError_t e;
   auto cleanup = [&](int rc) {
     if (cs) (void)hipStreamDestroy(cs);
+    if (p->ticket) (void)hipFree(p->ticket);
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
     delete p;
     return rc;
   };
+  // FP32 replays hand windows out dynamically from the plan's own counter
+  if (prec == IAAT_PREC_F32 && (e = hipMalloc((void**)&p->ticket, 256)) != hipSuccess)
+    return cleanup(fail(IAAT_ERR_NOMEM, "iaat_vbplan_create: ticket counter"));
   if ((e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking)) != hipSuccess ||
       (e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal)) != hipSuccess)
     return cleanup(hip_fail(e, "iaat_vbplan_create: capture setup"));
   if (count > 0) {
-    e = launch_batch(ctx, probs_dev, count, prec, status, cs);
+    e = launch_batch(ctx, probs_dev, count, prec, status, cs, p->ticket);
     if (e != hipSuccess) {
       hipGraph_t tmp = nullptr;
       (void)hipStreamEndCapture(cs, &tmp);
@@ -538,6 +542,7 @@ int iaat_vbplan_destroy(iaat_vbplan_t plan) {
   DeviceGuard g(plan->ctx->device);
   if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
   if (plan->graph) (void)hipGraphDestroy(plan->graph);
+  if (plan->ticket) (void)hipFree(plan->ticket);
   delete plan;
   return IAAT_OK;
 }

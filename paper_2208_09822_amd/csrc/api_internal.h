@@ -10,6 +10,7 @@
 
 struct iaat_vbplan {
   iaat_ctx* ctx = nullptr;
+  uint32_t* ticket = nullptr;  // the plan's window counter (cleared at each replay)
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int64_t count = 0;
@@ -52,6 +53,6 @@ struct DeviceGuard {
 
 // The batched launch(es) for one device descriptor array.
 hipError_t launch_batch(iaat_ctx_t ctx, const iaat_problem* probs_dev, int64_t count, int prec,
-                        int32_t* status, hipStream_t s);
+                        int32_t* status, hipStream_t s, uint32_t* ticket = nullptr);
 
 }  // namespace iaat

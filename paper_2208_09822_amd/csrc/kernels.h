@@ -26,6 +26,7 @@ struct VbArgs {
   int64_t count;
   int32_t* status;
   const PlanEntry* table;
+  uint32_t* ticket;  // NULL: windows dealt statically; else a counter handing them out
 };
 
 hipError_t launch_gemm_f32(const dev::Prob& P, int layout, const PlanEntry* table_dev, int nsm,

@@ -338,19 +338,29 @@ __device__ __forceinline__ int scan16(int v) {
   return v;
 }
 
+// The window after `win` for this work-group: the next of its static share
+// (window w to work-group w mod G), or -- with a ticket counter -- the next
+// window not yet handed out (windows 0..G-1 go to work-groups 0..G-1 first).
+__device__ __forceinline__ int64_t next_window(const VbArgs& a, int64_t win, int64_t G) {
+  if (a.ticket == nullptr) return win + G;
+  uint32_t t = 0;
+  if (lane() == 0) t = atomicAdd(a.ticket, 1u);
+  return G + (int64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)t);
+}
+
 // Wavefront 0 packs the next batch: problems of this work-group's windows,
 // in order, while they fit.  All bookkeeping is per lane (one problem per
 // lane) plus prefix sums, then every taken lane writes its own table
 // entries; so the cost per batch does not grow with the number of problems.
 __device__ __forceinline__ void pack_batch(const VbArgs& a, int64_t G, int64_t nwin, int64_t& win,
-                                           int& i, DescWindow& W0, DescWindow& W1, LaneProb& LP,
-                                           int tb) {
+                                           int64_t& win1, int& i, DescWindow& W0, DescWindow& W1,
+                                           LaneProb& LP, int tb) {
   const int l = lane();
   int used = 0, np = 0, nb = 0, nc = 0;
   bool more = true;
   for (;;) {
-    if (i == kWin) {  // window done: W1's words were read one window ahead
-      win += G;
+    if (i == kWin) {  // window done: W1 holds window win1's words, read one window ahead
+      win = win1;
       if (win >= nwin) {
         more = false;
         break;
@@ -359,7 +369,8 @@ __device__ __forceinline__ void pack_batch(const VbArgs& a, int64_t G, int64_t n
       W0 = W1;
       i = 0;
       LP = classify(W0, l < kWin && win * kWin + l < a.count);
-      if (win + G < nwin) window_load(W1, a, (win + G) * kWin);
+      win1 = next_window(a, win, G);
+      if (win1 < nwin) window_load(W1, a, win1 * kWin);
     }
     // candidates: lanes >= i that are staged
     const bool cand = l >= i && l < kWin && LP.cls == CLS_STAGE;
@@ -447,12 +458,14 @@ void vbatched_f32_kernel(VbArgs a) {
   DescWindow W0, W1;
   LaneProb LP{};
   int i = 0;
+  int64_t win1 = 0;  // the window after win (its words in W1)
   if (w == 0) {
     window_load(W0, a, win * kWin);
     window_load_plan(W0, a.table);
-    if (win + G < nwin) window_load(W1, a, (win + G) * kWin);
+    win1 = next_window(a, win, G);
+    if (win1 < nwin) window_load(W1, a, win1 * kWin);
     LP = classify(W0, lane() < kWin && win * kWin + lane() < a.count);
-    pack_batch(a, G, nwin, win, i, W0, W1, LP, 0);
+    pack_batch(a, G, nwin, win, win1, i, W0, W1, LP, 0);
   }
   lds_f* stage = (lds_f*)g_stage;
   __syncthreads();  // batch 0's tables
@@ -491,7 +504,7 @@ void vbatched_f32_kernel(VbArgs a) {
     }
     staged_barrier();  // batch t has landed
     if (w == 0) {
-      if (more) pack_batch(a, G, nwin, win, i, W0, W1, LP, t ^ 1);
+      if (more) pack_batch(a, G, nwin, win, win1, i, W0, W1, LP, t ^ 1);
     } else if (np > 0) {
       // blocks c, c + 7, ... on compute wavefront c = w - 1: lane u holds block c + 7u
       constexpr int kCompute = kWaves - 1;
@@ -589,6 +602,11 @@ __global__ __launch_bounds__(64) void vbatched_direct_kernel(VbArgs a) {
   }
 }
 
+// Clears a ticket counter (a kernel, so a captured graph holds no memset node).
+__global__ __launch_bounds__(64) void clear_ticket_kernel(uint32_t* t) {
+  if (threadIdx.x == 0) *t = 0;
+}
+
 __global__ __launch_bounds__(256) void copy_spans_kernel(const CopySpan* spans, int64_t count) {
   for (int64_t j = blockIdx.x; j < count; j += gridDim.x) {
     const CopySpan S = spans[j];
@@ -645,6 +663,11 @@ hipError_t launch_scale_f32(float* C, int m, int n, int ldc, float beta, hipStre
 }
 
 hipError_t launch_vbatched_f32(const VbArgs& a, int grid, int direct_grid, hipStream_t stream) {
+  if (a.ticket != nullptr) {
+    hipLaunchKernelGGL(dev::clear_ticket_kernel, dim3(1), dim3(64), 0, stream, a.ticket);
+    const hipError_t e0 = hipGetLastError();
+    if (e0 != hipSuccess) return e0;
+  }
   hipLaunchKernelGGL(dev::vbatched_f32_kernel, dim3((unsigned)grid), dim3(512), 0, stream, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
