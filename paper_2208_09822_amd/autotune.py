@@ -108,9 +108,11 @@ def _time_batch(ctx, torch, dev, layout, m, n, reps):
     buf = torch.from_numpy(ps.buf).to(dev)
     d = torch.from_numpy(iaat.descriptors(ps, buf.data_ptr()).view(np.uint8)).to(dev)
     s = torch.cuda.current_stream(dev)
+    # the graph-replayed batched launch, the form the tuned table serves
+    plan = iaat.iaat_vbplan_create(ctx, d.data_ptr(), count)
 
     def run():
-        iaat.iaat_gemm_vbatched_device(ctx, d.data_ptr(), count, stream=s.cuda_stream)
+        iaat.iaat_vbplan_launch(plan, s.cuda_stream)
 
     def measure():
         run()
@@ -122,6 +124,7 @@ def _time_batch(ctx, torch, dev, layout, m, n, reps):
         b.record(s)
         torch.cuda.synchronize(dev)
         return a.elapsed_time(b) / reps
+    measure.plan = plan
     return measure
 
 
@@ -156,6 +159,7 @@ def tune(out_path, reps=5, verbose=True):
                 first_t = t
             if t < best_t:
                 best, best_t = choice, t
+        iaat.iaat_vbplan_destroy(measure.plan)
         lines.append("%s %d %d %d %s %.2f %.2f" % (key[0], key[1], key[2], key[3], best,
                                                    best_t * 1e3, first_t * 1e3))
         if verbose:

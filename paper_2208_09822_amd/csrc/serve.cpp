@@ -44,6 +44,7 @@ struct Req {
 struct Launch {
   char* stage_host = nullptr;  // pinned
   char* stage_dev = nullptr;
+  uint32_t* ticket = nullptr;  // window counter of this slot's batched launches (one at a time)
   iaat_problem* desc_host = nullptr;
   CopySpan* cp_host = nullptr;
   hipEvent_t ev = nullptr;
@@ -225,7 +226,8 @@ struct iaat_server {
         e = launch_copy_spans((const CopySpan*)(L.stage_dev + dbytes), ncp,
                               (int)std::min<int64_t>(ncp, 4LL * ctx->num_cu), L.stream);
       if (e == hipSuccess)
-        e = launch_batch(ctx, (const iaat_problem*)L.stage_dev, n, cfg.prec, nullptr, L.stream);
+        e = launch_batch(ctx, (const iaat_problem*)L.stage_dev, n, cfg.prec, nullptr, L.stream,
+                         cfg.prec == IAAT_PREC_F32 ? L.ticket : nullptr);
       if (e == hipSuccess) e = hipEventRecord(L.ev, L.stream);
       lk.lock();
       if (e != hipSuccess) {  // the requests fail; the slot is reusable once the stream drains
@@ -265,6 +267,7 @@ static void free_server(iaat_server* S) {
     if (L.stage_host) (void)hipHostFree(L.stage_host);
     if (L.cp_host) (void)hipHostFree(L.cp_host);
     if (L.stage_dev) (void)hipFree(L.stage_dev);
+    if (L.ticket) (void)hipFree(L.ticket);
     if (L.ev) (void)hipEventDestroy(L.ev);
   }
   for (hipStream_t s : S->streams) (void)hipStreamDestroy(s);
@@ -303,6 +306,7 @@ int iaat_serve_start(iaat_ctx_t ctx, const iaat_serve_cfg* cfg, iaat_server_t* o
     if (e == hipSuccess) e = hipHostMalloc((void**)&L.stage_host, sbytes, 0);
     if (e == hipSuccess) e = hipHostMalloc((void**)&L.cp_host, mb * sizeof(CopySpan), 0);
     if (e == hipSuccess) e = hipMalloc((void**)&L.stage_dev, sbytes);
+    if (e == hipSuccess) e = hipMalloc((void**)&L.ticket, 256);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&L.ev, hipEventDisableTiming);
     L.desc_host = (iaat_problem*)L.stage_host;
   }
