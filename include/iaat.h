@@ -181,7 +181,7 @@ typedef struct iaat_problem {
  * the others are computed. */
 
 /* Computes every problem of a batch in one batched launch on `stream` (a
- * staging kernel whose work-groups each take windows of 16 problems, plus a
+ * staging kernel whose work-groups each take windows of 4 problems, plus a
  * companion kernel for problems too large to stage).  The descriptors are
  * already in device memory (`probs_dev`, count entries); validation,
  * tile-plan lookup and batching all run on the device, so the host does
@@ -244,7 +244,7 @@ int iaat_quantize_batch(iaat_ctx_t ctx, int prec, const iaat_qjob* jobs_dev, int
  * iaat_vbplan_create allocates and synchronises the device; launch does
  * neither.
  * create errors: -1 ctx, -2 probs_dev, -3 count, -4 prec, -6 out.
- * An FP32 plan hands the 16-problem windows out to work-groups dynamically
+ * An FP32 plan hands the 4-problem windows out to work-groups dynamically
  * from a counter the plan owns (cleared by a kernel at the start of each
  * replay), so replays of ONE plan must not overlap: launch them on one
  * stream, or wait between them.

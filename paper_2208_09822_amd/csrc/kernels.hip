@@ -150,23 +150,25 @@ __constant__ int kKidP2[IAAT_NUM_KIDS] = {
 // ---- batched kernel: staged batches --------------------------------------
 //
 // Work-groups of eight wavefronts, two per CU (each owns half of the LDS).
-// Problems are dealt to work-groups in windows of 16 consecutive problems
-// (window w to work-group w mod G).  Each iteration the work-group packs as
-// many of its next problems as fit into its staging buffer -- every
-// wavefront walks the same descriptors (16 per window, one per lane, with
-// their plan heads, read one window ahead) and copies its share of each
-// problem's A, B and (when beta != 0) C spans verbatim with memory-to-LDS
-// loads -- then waits once for all of them, and the eight wavefronts run the
-// batch's plan blocks round-robin from LDS and store C.  A barrier closes the
-// iteration because the buffer is refilled.  Problems that do not fit the
-// buffer are left to vbatched_direct_kernel; quick returns and status codes
-// are handled here.
+// Problems go to work-groups in windows of kWin consecutive problems: window
+// w to work-group w mod G, or, with a ticket counter, the first G windows so
+// and the rest to whichever work-group asks next (balancing the uneven
+// work).  Wavefront 0 packs a batch -- as many of the work-group's next
+// problems as fit into its staging buffer, one problem per lane, the
+// descriptors read a window ahead -- into one of two table sets.  Every
+// wavefront copies its share of the batch's A, B and (when beta != 0) C
+// spans verbatim into LDS with memory-to-LDS loads; after one wait,
+// wavefronts 1..7 run the batch's plan blocks round-robin from LDS and store
+// C while wavefront 0 packs the next batch.  A barrier closes the iteration
+// because the buffer is refilled.  Problems that do not fit the buffer are
+// left to vbatched_direct_kernel; quick returns and status codes are handled
+// here.
 
 constexpr int kStage = 19440;        // floats of staging per work-group (>= one 80x80x80 problem)
 constexpr int kMaxBatch = 16;        // problems per batch
 constexpr int kMaxBatchBlocks = 64;  // plan blocks per batch
 constexpr int kWaves = 8;
-constexpr int kWin = 16;             // problems per descriptor window
+constexpr int kWin = 4;              // problems per descriptor window
 
 struct BatchProb {  // 64 bytes
   float* C;
@@ -379,7 +381,7 @@ __device__ __forceinline__ void pack_batch(const VbArgs& a, int64_t G, int64_t n
     const int c_cnt = scan16(cand ? 1 : 0);
     const bool fits = used + c_need <= kStage && nb + c_blk <= kMaxBatchBlocks && np + c_cnt <= kMaxBatch;
     // first staged lane that does not fit ends this batch
-    const uint64_t stop = __ballot(cand && !fits) & 0xffffull;
+    const uint64_t stop = __ballot(cand && !fits) & ((1ull << kWin) - 1);
     const int end = stop ? __builtin_ctzll(stop) : kWin;
     const bool take = l >= i && l < end;  // consumed by this batch
     const int64_t q = win * kWin + l;
