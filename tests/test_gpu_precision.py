@@ -17,7 +17,7 @@ import torch
 import oracle
 from oracle import quant
 from paper_2208_09822_amd import iaat, inputs
-from oracle.metrics import abs_product_norm, scaled_rel
+from oracle import lowp, metrics
 from _helpers import fp32_equal, normwise, result_of
 
 pytestmark = pytest.mark.gpu
@@ -39,20 +39,13 @@ def stream():
     return torch.cuda.current_stream(DEV).cuda_stream
 
 
+MODE = {iaat.IAAT_PREC_BF16: "bf16", iaat.IAAT_PREC_F16: "f16", iaat.IAAT_PREC_F8E4M3: "e4m3",
+        iaat.IAAT_PREC_BF16X3: "bf16x3"}
+
+
 def oracle_quant(prec, x):
-    """(dequantised FP64 operand terms, scale) of an FP32 master array:
-    a list of one array, or [hi, lo] for split-bfloat16."""
-    x64 = np.asarray(x, np.float32).astype(np.float64)
-    if prec == iaat.IAAT_PREC_BF16:
-        return [quant.bf16_round(x64)], 1.0
-    if prec == iaat.IAAT_PREC_F16:
-        return [quant.f16_round(x64)], 1.0
-    if prec == iaat.IAAT_PREC_F8E4M3:
-        amax = float(np.max(np.abs(x64))) if x64.size else 0.0
-        s = quant.fp8_scale(amax)
-        return [quant.e4m3_round(x64 * s) / s], s
-    hi, lo = quant.split_bf16(x64)
-    return [hi, lo], 1.0
+    """(dequantised FP64 operand terms, scale) of an FP32 master array."""
+    return lowp.dequant_terms(MODE[prec], x)
 
 
 def decode(prec, codes):
@@ -84,41 +77,19 @@ def run_lowp(ctx, ps, prec):
 
 def oracle_lowp(ps, q, prec):
     t = int(ps.trans[q])
-    a_terms, sa = oracle_quant(prec, ps.A(q))
-    b_terms, sb = oracle_quant(prec, ps.B(q))
-    args = (t & 1, t >> 1, int(ps.m[q]), int(ps.n[q]), int(ps.k[q]), float(ps.alpha[q]))
-    lda, ldb, ldc = int(ps.lda[q]), int(ps.ldb[q]), int(ps.ldc[q])
-    if prec != iaat.IAAT_PREC_BF16X3:
-        return oracle.gemm_dequant(*args, a_terms[0], lda, b_terms[0], ldb, float(ps.beta[q]),
-                                   ps.C(q), ldc), sa, sb
-    (ah, al), (bh, bl) = a_terms, b_terms
-    r = oracle.gemm_dequant(*args, ah, lda, bh, ldb, float(ps.beta[q]), ps.C(q), ldc)
-    r = r + oracle.gemm_dequant(*args, ah, lda, bl, ldb, 0.0, None, ldc)
-    r = r + oracle.gemm_dequant(*args, al, lda, bh, ldb, 0.0, None, ldc)
-    return r, sa, sb
-
-
-def op_abs(arr, ld, rows, cols, trans):
-    """|op(X)| of a stored column-major matrix (FP64)."""
-    x = np.abs(np.asarray(arr, np.float64)[:ld * cols].reshape(cols, ld).T[:rows, :])
-    return x.T if trans else x
+    return lowp.gemm_lowp(MODE[prec], t & 1, t >> 1, int(ps.m[q]), int(ps.n[q]), int(ps.k[q]),
+                          float(ps.alpha[q]), ps.A(q), int(ps.lda[q]), ps.B(q), int(ps.ldb[q]),
+                          float(ps.beta[q]), ps.C(q), int(ps.ldc[q]))
 
 
 def scaled_error(ps, q, prec, got, ref):
     """||C-hat - C*||_F / (|alpha| || |op(A)||op(B)| ||_F + |beta| ||C0||_F) on
     the dequantised operands (hi + lo magnitudes for split-bfloat16)."""
     t = int(ps.trans[q])
-    m, n, k = int(ps.m[q]), int(ps.n[q]), int(ps.k[q])
-    a_terms, _ = oracle_quant(prec, ps.A(q))
-    b_terms, _ = oracle_quant(prec, ps.B(q))
-    a = sum(np.abs(x) for x in a_terms)
-    b = sum(np.abs(x) for x in b_terms)
-    ra, ca = (k, m) if t & 1 else (m, k)
-    rb, cb = (n, k) if t & 2 else (k, n)
-    ab = abs_product_norm(op_abs(a, int(ps.lda[q]), ra, ca, t & 1),
-                          op_abs(b, int(ps.ldb[q]), rb, cb, t & 2)) if k > 0 else 0.0
-    c0 = np.asarray(ps.C(q), np.float64)[:int(ps.ldc[q]) * n].reshape(n, int(ps.ldc[q])).T[:m, :]
-    return scaled_rel(got, ref, float(ps.alpha[q]), ab, float(ps.beta[q]), np.linalg.norm(c0))
+    return metrics.scaled_error(got, ref, t & 1, t >> 1, int(ps.m[q]), int(ps.n[q]), int(ps.k[q]),
+                                float(ps.alpha[q]), lowp.abs_terms(MODE[prec], ps.A(q)),
+                                int(ps.lda[q]), lowp.abs_terms(MODE[prec], ps.B(q)), int(ps.ldb[q]),
+                                float(ps.beta[q]), ps.C(q), int(ps.ldc[q]))
 
 
 def grid_shapes(step=3):

@@ -120,9 +120,25 @@ def test_fig2_fifteen_by_fifteen():
     assert tiler_ref.strip_dp_optimum(15, 15) == a
 
 
-def test_table1_counts():
-    want = golden_rows("table1_kernel_counts.txt")
-    assert [tiler_ref.kernel_count(t) for t in "SDCZ"] == [want[t][0] for t in "SDCZ"]
+def test_table1_kernel_sets():
+    """The transcription in tiler_ref equals an independent row-by-row
+    transcription of Table 1 (tests/golden/table1_kernels.txt) for every type
+    and layout; the per-type totals are derived from the rows (the table
+    prints none)."""
+    rows = {}
+    for line in open(os.path.join(GOLDEN, "table1_kernels.txt")):
+        f = line.split("#")[0].split()
+        if not f:
+            continue
+        typ, lay, fixed, cnt = f[0], f[1], int(f[2]), int(f[3])
+        ks = rows.setdefault((typ, lay), set())
+        for v in range(1, cnt + 1):
+            ks.add((v, fixed) if lay == "TT" else (fixed, v))
+    assert len(rows) == 16
+    for (typ, lay), ks in rows.items():
+        assert tiler_ref.kernel_set(typ, lay) == ks, (typ, lay)
+    totals = {t: sum(len(rows[(t, l)]) for l in ("NN", "NT", "TN", "TT")) for t in "SDCZ"}
+    assert [tiler_ref.kernel_count(t) for t in "SDCZ"] == [totals[t] for t in "SDCZ"]
 
 
 @pytest.mark.parametrize("M", range(1, 81))
