@@ -254,6 +254,28 @@ int iaat_vbplan_create(iaat_ctx_t ctx, const iaat_problem* probs_dev, int64_t co
 int iaat_vbplan_launch(iaat_vbplan_t plan, iaat_stream_t stream);
 int iaat_vbplan_destroy(iaat_vbplan_t plan); /* NULL accepted */
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the FP32
+ * batched launch of iaat_vbplan_* (4-problem windows handed out to
+ * work-groups from a counter, which balances uneven batches) without a plan
+ * object.  The counter lives in a fixed 256-byte array of device memory that
+ * the library holds on each GPU until the process ends; its address is
+ * taken once per device by iaat_create.  No call here allocates or frees
+ * memory.  A kernel clears the counter at the start of every call, so the
+ * array keeps nothing a later call relies on; but every call on one GPU
+ * uses the same array, so calls that may run at the same time on one GPU
+ * (different streams, contexts or threads) race and must be serialised by
+ * the caller.  Results are bitwise those of iaat_gemm_vbatched_device and
+ * iaat_vbplan_launch on the same descriptors.
+ *   probs_dev: device array of count descriptors (FP32: ab_scale 1 or the
+ *   factor on op(A)op(B)); count in [0, 2^31 - 1] (the counter's range);
+ *   status: NULL or a device array of count int32 (as the batched forms).
+ * Errors: -1 ctx, -2 probs_dev NULL with count > 0, -3 count outside
+ * [0, 2^31 - 1], IAAT_ERR_HIP (launch, or no scratch address on the
+ * context's device). */
+int iaat_gemm_vbatched_noalloc(iaat_ctx_t ctx, const iaat_problem* probs_dev, int64_t count,
+                               int32_t* status, iaat_stream_t stream);
+
 /* ------------------------------------------------ ablation: traditional */
 
 /* The traditional small-GEMM scheme that IAAT replaces (Section I; Fig. 2(a)

@@ -157,6 +157,10 @@ int iaat_create(iaat_ctx_t* out, int device, const char* tile_table_path) {
   }
   c->vb_grid = per_cu * c->num_cu;
   c->direct_grid = direct_per_cu * c->num_cu;
+  if ((e = scratch_init(device)) != hipSuccess) {
+    free_ctx(c);
+    return hip_fail(e, "iaat_create: scratch address");
+  }
 
   const size_t tbytes = sizeof(PlanEntry) * c->table.size();
   if (hipMalloc(&c->table_dev, tbytes) != hipSuccess) {
@@ -481,6 +485,27 @@ int iaat_gemm_vbatched_device(iaat_ctx_t ctx, const iaat_problem* probs_dev, int
   hipStream_t s = (hipStream_t)stream;
   const hipError_t e = launch_batch(ctx, probs_dev, count, prec, status, s);
   return e == hipSuccess ? IAAT_OK : hip_fail(e, "iaat_gemm_vbatched_device: launch");
+}
+
+// Largest batch of the allocation-free form: the window counter in the
+// device scratch is 32 bits wide.
+constexpr int64_t kNoAllocMaxCount = 0x7fffffffLL;
+
+int iaat_gemm_vbatched_noalloc(iaat_ctx_t ctx, const iaat_problem* probs_dev, int64_t count,
+                               int32_t* status, iaat_stream_t stream) {
+  if (!ctx) return fail(-1, "iaat_gemm_vbatched_noalloc: ctx is NULL");
+  if (count < 0 || count > kNoAllocMaxCount)
+    return fail(-3, "iaat_gemm_vbatched_noalloc: count=%lld outside [0, %lld] (the scratch "
+                "window counter is 32 bits)", (long long)count, (long long)kNoAllocMaxCount);
+  if (count > 0 && !probs_dev) return fail(-2, "iaat_gemm_vbatched_noalloc: probs is NULL");
+  if (count == 0) return IAAT_OK;
+  uint32_t* ticket = scratch_address(ctx->device);
+  if (!ticket) return fail(IAAT_ERR_HIP, "iaat_gemm_vbatched_noalloc: no scratch on device %d",
+                           ctx->device);
+  DeviceGuard g(ctx->device);
+  const hipError_t e = launch_batch(ctx, probs_dev, count, IAAT_PREC_F32, status,
+                                    (hipStream_t)stream, ticket);
+  return e == hipSuccess ? IAAT_OK : hip_fail(e, "iaat_gemm_vbatched_noalloc: launch");
 }
 
 int iaat_vbplan_create(iaat_ctx_t ctx, const iaat_problem* probs_dev, int64_t count, int prec,

@@ -40,6 +40,15 @@ hipError_t launch_scale_f32_strided(float* C, int m, int n, int ldc, float beta,
 hipError_t launch_vbatched_f32(const VbArgs& a, int grid, int direct_grid, hipStream_t stream);
 hipError_t vbatched_occupancy(int* blocks_per_cu, int* direct_per_cu);
 
+// Scratch of the allocation-free batched entry point (a file-scope device
+// array in kernels.hip, kScratchWords 32-bit words).  scratch_init(device)
+// takes its address on `device` (which must be current) once; afterwards
+// scratch_address(device) returns it (NULL before scratch_init).
+constexpr int kScratchWords = 64;
+constexpr int kMaxDevices = 64;
+hipError_t scratch_init(int device);
+uint32_t* scratch_address(int device);
+
 
 // Copies float spans (src, dst, n floats), one work-group per span.
 struct CopySpan {

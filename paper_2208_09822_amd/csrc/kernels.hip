@@ -6,6 +6,8 @@
 // used by the serving loop.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "iaat_internal.h"
 #include "kernels.h"
 #include "lds_tiles.h"
@@ -616,9 +618,40 @@ __global__ __launch_bounds__(256) void copy_spans_kernel(const CopySpan* spans, 
   }
 }
 
+// Device scratch of the allocation-free batched entry point: word 0 is the
+// window counter that hands 4-problem windows out to work-groups.  Each GPU
+// the library runs on holds its own copy until the process ends.  In host
+// code the name is only a stand-in: the device address comes from
+// scratch_address(), taken once per device.
+static __device__ __align__(256) uint32_t scratch[kScratchWords];
+
 }  // namespace dev
 
 // ------------------------------------------------------------ host launchers
+
+namespace {
+std::mutex g_scratch_mu;
+uint32_t* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t scratch_init(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device] != nullptr) return hipSuccess;
+  // the caller made `device` current
+  uint32_t* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(dev::scratch));
+  if (e != hipSuccess) return e;
+  if (ptr == nullptr) return hipErrorInvalidSymbol;
+  g_scratch_ptr[device] = ptr;
+  return hipSuccess;
+}
+
+uint32_t* scratch_address(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_ptr[device];
+}
 
 hipError_t launch_copy_spans(const CopySpan* spans, int64_t count, int grid, hipStream_t stream) {
   hipLaunchKernelGGL(dev::copy_spans_kernel, dim3((unsigned)grid), dim3(256), 0, stream, spans, count);

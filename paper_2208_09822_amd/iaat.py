@@ -110,6 +110,7 @@ def lib():
                                     vp, i64, vp]),
                 "iaat_gemm_vbatched_device": (i32, [vp, vp, i64, i32, vp, vp]),
                 "iaat_gemm_vbatched": (i32, [vp, vp, i64, i32, vp, vp]),
+                "iaat_gemm_vbatched_noalloc": (i32, [vp, vp, i64, vp, vp]),
                 "iaat_vbplan_create": (i32, [vp, vp, i64, i32, vp, ctypes.POINTER(vp)]),
                 "iaat_quantize_batch": (i32, [vp, i32, vp, i64, vp]),
                 "iaat_trad_create": (i32, [vp, vp, i64, ctypes.POINTER(vp)]),
@@ -187,6 +188,11 @@ def iaat_gemm_vbatched_device(ctx, probs_dev, count, prec=IAAT_PREC_F32, status=
                               stream=0) -> None:
     _check(lib().iaat_gemm_vbatched_device(ctx, probs_dev or None, int(count), int(prec),
                                            status or None, stream or None))
+
+
+def iaat_gemm_vbatched_noalloc(ctx, probs_dev, count, status=0, stream=0) -> None:
+    _check(lib().iaat_gemm_vbatched_noalloc(ctx, probs_dev or None, int(count), status or None,
+                                            stream or None))
 
 
 def iaat_gemm_vbatched(ctx, probs_host: np.ndarray, count=None, prec=IAAT_PREC_F32, status=0,
