@@ -101,9 +101,10 @@ hipError_t launch_batch(iaat_ctx_t ctx, const iaat_problem* probs_dev, int64_t c
     const int64_t cap = 8LL * ctx->num_cu;  // work-groups of 256 threads, grid-stride over problems
     return launch_vbatched_lowp(a, prec, (int)(count < cap ? count : cap), s);
   }
-  const int grid = (int)(count < ctx->vb_grid ? count : ctx->vb_grid);
-  const int dgrid = (int)((count + 63) / 64);  // one screening wavefront per 64 problems
-  return launch_vbatched_f32(a, grid, dgrid, s);
+  // work-groups take 4-problem windows
+  const int64_t units = (count + 3) / 4;
+  const int grid = (int)(units < ctx->vb_grid ? units : ctx->vb_grid);
+  return launch_vbatched_f32(a, grid, s);
 }
 
 }  // namespace iaat
@@ -149,19 +150,12 @@ int iaat_create(iaat_ctx_t* out, int device, const char* tile_table_path) {
     free_ctx(c);
     return hip_fail(e, "iaat_create: device attribute");
   }
-  int per_cu = 0, direct_per_cu = 0;
-  if ((e = vbatched_occupancy(&per_cu, &direct_per_cu)) != hipSuccess || per_cu < 1 ||
-      direct_per_cu < 1) {
+  int per_cu = 0;
+  if ((e = vbatched_occupancy(&per_cu)) != hipSuccess || per_cu < 1) {
     free_ctx(c);
     return hip_fail(e, "iaat_create: occupancy");
   }
   c->vb_grid = per_cu * c->num_cu;
-  c->direct_grid = direct_per_cu * c->num_cu;
-  if ((e = scratch_init(device)) != hipSuccess) {
-    free_ctx(c);
-    return hip_fail(e, "iaat_create: scratch address");
-  }
-
   const size_t tbytes = sizeof(PlanEntry) * c->table.size();
   if (hipMalloc(&c->table_dev, tbytes) != hipSuccess) {
     free_ctx(c);

@@ -19,8 +19,7 @@ struct iaat_vbplan {
 struct iaat_ctx {
   int device = 0;
   int num_cu = 0;
-  int vb_grid = 0;      // staged batched kernel: work-groups resident at once
-  int direct_grid = 0;  // direct batched kernel: wavefronts resident at once
+  int vb_grid = 0;      // batched kernel: work-groups resident at once
   std::vector<iaat::PlanEntry> table;   // the plans in use (host copy of table_dev)
   iaat::PlanEntry* table_dev = nullptr;
   std::vector<iaat::PlanEntry> staged;  // iaat_plan_set edits, applied by iaat_table_commit

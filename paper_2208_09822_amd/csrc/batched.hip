@@ -1,0 +1,970 @@
+// The batched FP32 kernel: many uneven problems in one persistent launch.
+//
+// Work-groups stage batches of problems in LDS and run their kernel
+// executing plans (Section V-B) from there; problems too large to stage go
+// to a companion kernel that reads them straight from memory.
+//
+// The staged copies are verbatim: each operand's memory span (A, B, and C
+// when beta != 0) is copied with 16-byte memory-to-LDS loads and keeps its
+// leading dimension, so element (r, c) of a stored matrix sits at
+// la + r + c*ld.  This is the GPU counterpart of the paper's operands
+// sitting in cache: no reordering and no extra memory traffic (each element
+// crosses HBM once), so not a pack step.
+//
+// A problem's plan blocks are run as units: compile-time-sized members of
+// the generated family or pieces of one (a pair of matrix-core tiles, a
+// strip of at most four rows or columns, a K-split row).  Cutting a block
+// into pieces never changes an element's arithmetic, and each unit performs
+// exactly the operations of its direct-from-memory counterpart in tiles.h,
+// in the same order, so a problem gets bitwise the same C here as from
+// iaat_gemm.
+#include <hip/hip_runtime.h>
+
+#include "direct.h"
+#include "iaat_internal.h"
+#include "kernels.h"
+#include "tiles.h"
+
+namespace iaat {
+namespace dev {
+
+typedef __attribute__((address_space(3))) float lds_f;
+
+struct SProb {
+  const lds_f* a;
+  const lds_f* b;
+  const lds_f* c;  // staged C, or null: C is read from memory (when beta != 0)
+  float* C;
+  int m, n, k;
+  int lda, ldb, ldc;  // lda, ldb: staged; ldc: memory
+  int ldcs;           // staged ldc
+  float alpha, beta;
+};
+
+// C(i, j) for the epilogue: from memory (CMEM), else the staged copy, or 0
+// when beta == 0.  The compute loop inlines only the CMEM = false forms:
+// a memory load there would make the compiler wait on the vector-memory
+// counter, which on this architecture also counts the wavefront's earlier
+// C stores.
+template <bool CMEM>
+__device__ __forceinline__ float c_at(const SProb& P, rsrc_t rc, int i, int j) {
+  if (P.beta == 0.0f) return 0.0f;
+  if (CMEM) return bld(rc, 4 * ((uint32_t)i + (uint32_t)j * (uint32_t)P.ldc));
+  return P.c[i + j * P.ldcs];
+}
+
+template <int TA>
+__device__ __forceinline__ float sa(const SProb& P, int i, int k) {
+  return TA ? P.a[k + i * P.lda] : P.a[i + k * P.lda];
+}
+template <int TB>
+__device__ __forceinline__ float sb(const SProb& P, int k, int j) {
+  return TB ? P.b[j + k * P.ldb] : P.b[k + j * P.ldb];
+}
+// Four consecutive staged floats.  The staged copies keep the operands'
+// memory alignment, so these are four 4-byte reads.
+__device__ __forceinline__ f4 ld4(const lds_f* p) { return f4{p[0], p[1], p[2], p[3]}; }
+
+// The lane index, read afresh in every unit: a volatile read cannot be
+// hoisted out of the compute loop, so the lane-derived values of the many
+// inlined units are not all kept live across it.
+__device__ __forceinline__ int lane_u() {
+  int v;
+  asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(v));
+  return v;
+}
+
+__device__ __forceinline__ float epi_c(float alpha, float acc, float beta, float c) {
+  return beta == 0.0f ? alpha * acc : fmaf(alpha, acc, beta * c);
+}
+
+// TM x TN (<= 2 x 2) tiles of 16 x 16 with v_mfma_f32_16x16x4_f32, the
+// operation sequence of MfmaBlock: chunks of 16 k, step s of a chunk gives
+// lane group g = l/16 the reduction index 4g + s; the last partial chunk
+// reads k = min(4g + s, rem - 1) and contributes zero past rem.
+template <int TA, int TB, int TM, int TN, bool CMEM>
+struct StagedMfma {
+  static __device__ __forceinline__ void run(const SProb& P, int i0, int j0) {
+    const int l = lane_u();
+    const int r = l & 15, g = l >> 4;
+    const rsrc_t rc = rsrc(P.C);
+    const uint32_t ldc = (uint32_t)P.ldc;
+    const float alpha = P.alpha, beta = P.beta;
+    // C first, so its memory latency overlaps the K loop
+    f4 cv[TM][TN];
+#pragma unroll
+    for (int tn = 0; tn < TN; ++tn)
+#pragma unroll
+      for (int tm = 0; tm < TM; ++tm) {
+        cv[tm][tn] = f4{0.f, 0.f, 0.f, 0.f};
+        const int j = j0 + 16 * tn + r, ib = i0 + 16 * tm + 4 * g;
+        if (!CMEM || beta == 0.0f || j >= P.n) continue;
+        const uint32_t oc = 4 * ((uint32_t)ib + (uint32_t)j * ldc);
+        if (ib + 3 < P.m) {
+          const f4u c = bld4(rc, oc);
+          cv[tm][tn] = f4{c.x, c.y, c.z, c.w};
+        } else {
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            if (ib + v < P.m) cv[tm][tn][v] = bld(rc, oc + 4 * v);
+        }
+      }
+    // per-lane element offsets of this lane's op(A) row / op(B) column at
+    // k-slot 4g of chunk 0
+    int oa[TM], ob[TN];
+#pragma unroll
+    for (int t = 0; t < TM; ++t) {
+      const int i = min(i0 + 16 * t + r, P.m - 1);
+      oa[t] = TA ? i * P.lda + 4 * g : i + 4 * g * P.lda;
+    }
+#pragma unroll
+    for (int t = 0; t < TN; ++t) {
+      const int j = min(j0 + 16 * t + r, P.n - 1);
+      ob[t] = TB ? j + 4 * g * P.ldb : j * P.ldb + 4 * g;
+    }
+    const int da = TA ? 16 : 16 * P.lda, db = TB ? 16 * P.ldb : 16;  // per chunk
+    f4 acc[TM][TN];
+#pragma unroll
+    for (int tm = 0; tm < TM; ++tm)
+#pragma unroll
+      for (int tn = 0; tn < TN; ++tn) acc[tm][tn] = f4{0.f, 0.f, 0.f, 0.f};
+    const int nfull = P.k >> 4;
+    const lds_f* pa = P.a;
+    const lds_f* pb = P.b;
+    // Chunks are double-buffered in registers: the fragments of chunk c+1
+    // are read from LDS while chunk c's four steps run on the matrix core.
+    struct Frag {
+      f4 a[TM], b[TN];
+    };
+    auto load = [&](Frag& f, const lds_f* qa, const lds_f* qb) {
+#pragma unroll
+      for (int t = 0; t < TM; ++t) {
+        if (TA) {
+          f.a[t] = ld4(qa + oa[t]);
+        } else {
+#pragma unroll
+          for (int s = 0; s < 4; ++s) f.a[t][s] = qa[oa[t] + s * P.lda];
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < TN; ++t) {
+        if (!TB) {
+          f.b[t] = ld4(qb + ob[t]);
+        } else {
+#pragma unroll
+          for (int s = 0; s < 4; ++s) f.b[t][s] = qb[ob[t] + s * P.ldb];
+        }
+      }
+    };
+    auto mma = [&](const Frag& f) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int tm = 0; tm < TM; ++tm)
+#pragma unroll
+          for (int tn = 0; tn < TN; ++tn)
+            acc[tm][tn] = __builtin_amdgcn_mfma_f32_16x16x4f32(f.a[tm][s], f.b[tn][s], acc[tm][tn], 0, 0, 0);
+    };
+    if (nfull > 0) {
+      Frag f0, f1;
+      load(f0, pa, pb);
+      for (int c = 0; c < nfull; c += 2) {
+        if (c + 1 < nfull) load(f1, pa + da, pb + db);
+        __builtin_amdgcn_sched_barrier(0);
+        mma(f0);
+        if (c + 1 >= nfull) {
+          pa += da;
+          pb += db;
+          break;
+        }
+        if (c + 2 < nfull) load(f0, pa + 2 * da, pb + 2 * db);
+        __builtin_amdgcn_sched_barrier(0);
+        mma(f1);
+        pa += 2 * da;
+        pb += 2 * db;
+      }
+    }
+    const int rem = P.k - (nfull << 4);
+    if (rem > 0) {
+      f4 va[TM], vb[TN];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int kk = 4 * g + s;
+        const bool ok = kk < rem;
+        const int kc = min(kk, rem - 1);
+#pragma unroll
+        for (int t = 0; t < TM; ++t) {
+          const float v = TA ? pa[oa[t] - 4 * g + kc] : pa[oa[t] - 4 * g * P.lda + kc * P.lda];
+          va[t][s] = ok ? v : 0.0f;
+        }
+#pragma unroll
+        for (int t = 0; t < TN; ++t) {
+          const float v = TB ? pb[ob[t] - 4 * g * P.ldb + kc * P.ldb] : pb[ob[t] - 4 * g + kc];
+          vb[t][s] = ok ? v : 0.0f;
+        }
+      }
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int tm = 0; tm < TM; ++tm)
+#pragma unroll
+          for (int tn = 0; tn < TN; ++tn)
+            acc[tm][tn] = __builtin_amdgcn_mfma_f32_16x16x4f32(va[tm][s], vb[tn][s], acc[tm][tn], 0, 0, 0);
+    }
+    if (!CMEM && beta != 0.0f) {  // staged C
+#pragma unroll
+      for (int tn = 0; tn < TN; ++tn) {
+        const int j = min(j0 + 16 * tn + r, P.n - 1);
+#pragma unroll
+        for (int tm = 0; tm < TM; ++tm) {
+          const int ib = i0 + 16 * tm + 4 * g;
+          const lds_f* pc = P.c + j * P.ldcs;
+          if (ib + 3 < P.m && (ib & 3) == 0) {
+            cv[tm][tn] = ld4(pc + ib);
+          } else {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) cv[tm][tn][v] = pc[min(ib + v, P.m - 1)];
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int tn = 0; tn < TN; ++tn) {
+      const int j = j0 + 16 * tn + r;
+      if (j >= P.n) continue;
+#pragma unroll
+      for (int tm = 0; tm < TM; ++tm) {
+        const int ib = i0 + 16 * tm + 4 * g;
+        const uint32_t oc = 4 * ((uint32_t)ib + (uint32_t)j * ldc);
+        if (ib + 3 < P.m) {
+          f4u o;
+          o.x = epi_c(alpha, acc[tm][tn].x, beta, cv[tm][tn].x);
+          o.y = epi_c(alpha, acc[tm][tn].y, beta, cv[tm][tn].y);
+          o.z = epi_c(alpha, acc[tm][tn].z, beta, cv[tm][tn].z);
+          o.w = epi_c(alpha, acc[tm][tn].w, beta, cv[tm][tn].w);
+          bst4(rc, oc, o);
+        } else {
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            if (ib + v < P.m) bst(rc, oc + 4 * v, epi_c(alpha, acc[tm][tn][v], beta, cv[tm][tn][v]));
+        }
+      }
+    }
+  }
+};
+
+// MR rows x 64 columns, lane = column (RowsBlock's operation sequence: FMA
+// chains over k in increasing order, four k at a time, then the rest).
+template <int TA, int TB, int MR, bool CMEM>
+struct StagedRows {
+  static __device__ __forceinline__ void run(const SProb& P, int i0, int j0) {
+    const int j = j0 + lane_u();
+    const int jc = min(j, P.n - 1);
+    const rsrc_t rc = rsrc(P.C);
+    const uint32_t oc = 4 * ((uint32_t)i0 + (uint32_t)j * (uint32_t)P.ldc);
+    const bool st = j < P.n;
+    float cv[MR];
+#pragma unroll
+    for (int i = 0; i < MR; ++i) cv[i] = (CMEM && st) ? c_at<true>(P, rc, i0 + i, j) : 0.0f;
+    float acc[MR];
+#pragma unroll
+    for (int i = 0; i < MR; ++i) acc[i] = 0.0f;
+    const int K = P.k;
+    int k = 0;
+    for (; k + 4 <= K; k += 4) {
+      f4 b;
+      if (!TB) {
+        b = ld4(P.b + jc * P.ldb + k);
+      } else {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) b[s] = P.b[jc + (k + s) * P.ldb];
+      }
+      f4 a[MR];
+#pragma unroll
+      for (int i = 0; i < MR; ++i) {
+        if (TA) {
+          a[i] = ld4(P.a + (i0 + i) * P.lda + k);
+        } else {
+#pragma unroll
+          for (int s = 0; s < 4; ++s) a[i][s] = P.a[(i0 + i) + (k + s) * P.lda];
+        }
+      }
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int i = 0; i < MR; ++i) acc[i] = fmaf(a[i][s], b[s], acc[i]);
+    }
+    for (; k < K; ++k) {
+      const float b = sb<TB>(P, k, jc);
+#pragma unroll
+      for (int i = 0; i < MR; ++i) acc[i] = fmaf(sa<TA>(P, i0 + i, k), b, acc[i]);
+    }
+    if (!CMEM) {
+#pragma unroll
+      for (int i = 0; i < MR; ++i) cv[i] = c_at<false>(P, rc, i0 + i, jc);
+    }
+    if (st) {
+#pragma unroll
+      for (int i = 0; i < MR; ++i) bst(rc, oc + 4 * i, epi_c(P.alpha, acc[i], P.beta, cv[i]));
+    }
+  }
+};
+
+// 64 rows x NR columns, lane = row (mirror image of the row strip).
+template <int TA, int TB, int NR, bool CMEM>
+struct StagedCols {
+  static __device__ __forceinline__ void run(const SProb& P, int i0, int j0) {
+    const int i = i0 + lane_u();
+    const int ic = min(i, P.m - 1);
+    const rsrc_t rc = rsrc(P.C);
+    const uint32_t ldc = (uint32_t)P.ldc;
+    const bool st = i < P.m;
+    float cv[NR];
+#pragma unroll
+    for (int j = 0; j < NR; ++j) cv[j] = (CMEM && st) ? c_at<true>(P, rc, i, j0 + j) : 0.0f;
+    float acc[NR];
+#pragma unroll
+    for (int j = 0; j < NR; ++j) acc[j] = 0.0f;
+    const int K = P.k;
+    int k = 0;
+    for (; k + 4 <= K; k += 4) {
+      f4 a;
+      if (TA) {
+        a = ld4(P.a + ic * P.lda + k);
+      } else {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) a[s] = P.a[ic + (k + s) * P.lda];
+      }
+      f4 b[NR];
+#pragma unroll
+      for (int j = 0; j < NR; ++j) {
+        if (!TB) {
+          b[j] = ld4(P.b + (j0 + j) * P.ldb + k);
+        } else {
+#pragma unroll
+          for (int s = 0; s < 4; ++s) b[j][s] = P.b[(j0 + j) + (k + s) * P.ldb];
+        }
+      }
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int j = 0; j < NR; ++j) acc[j] = fmaf(a[s], b[j][s], acc[j]);
+    }
+    for (; k < K; ++k) {
+      const float a = sa<TA>(P, ic, k);
+#pragma unroll
+      for (int j = 0; j < NR; ++j) acc[j] = fmaf(a, sb<TB>(P, k, j0 + j), acc[j]);
+    }
+    if (!CMEM) {
+#pragma unroll
+      for (int j = 0; j < NR; ++j) cv[j] = c_at<false>(P, rc, ic, j0 + j);
+    }
+    if (st) {
+#pragma unroll
+      for (int j = 0; j < NR; ++j)
+        bst(rc, 4 * ((uint32_t)i + (uint32_t)(j0 + j) * ldc), epi_c(P.alpha, acc[j], P.beta, cv[j]));
+    }
+  }
+};
+
+// MR x NR (<= 4 x 4) block, K split over the lanes: lane l sums k = l,
+// l + 64, ...; a butterfly adds the 64 partial sums; lane 0 stores
+// (KredBlock's operation sequence).
+template <int TA, int TB, int MR, int NR, bool CMEM>
+struct StagedKred {
+  static __device__ __forceinline__ void run(const SProb& P, int i0, int j0) {
+    const int l = lane_u();
+    float acc[MR][NR];
+#pragma unroll
+    for (int i = 0; i < MR; ++i)
+#pragma unroll
+      for (int j = 0; j < NR; ++j) acc[i][j] = 0.0f;
+    for (int kb = 0; kb < P.k; kb += 64) {
+      const int k = kb + l;
+      if (k < P.k) {
+        float a[MR], b[NR];
+#pragma unroll
+        for (int i = 0; i < MR; ++i) a[i] = sa<TA>(P, i0 + i, k);
+#pragma unroll
+        for (int j = 0; j < NR; ++j) b[j] = sb<TB>(P, k, j0 + j);
+#pragma unroll
+        for (int i = 0; i < MR; ++i)
+#pragma unroll
+          for (int j = 0; j < NR; ++j) acc[i][j] = fmaf(a[i], b[j], acc[i][j]);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < MR; ++i)
+#pragma unroll
+      for (int j = 0; j < NR; ++j) {
+        float v = acc[i][j];
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+        acc[i][j] = v;
+      }
+    if (l == 0) {
+      const uint32_t ldc = (uint32_t)P.ldc;
+      const rsrc_t rc = rsrc(P.C);
+#pragma unroll
+      for (int j = 0; j < NR; ++j)
+#pragma unroll
+        for (int i = 0; i < MR; ++i)
+          bst(rc, 4 * ((uint32_t)(i0 + i) + (uint32_t)(j0 + j) * ldc),
+              epi_c(P.alpha, acc[i][j], P.beta, c_at<CMEM>(P, rc, i0 + i, j0 + j)));
+    }
+  }
+};
+
+// The units the batched kernel runs.  Each is a compile-time-sized member of
+// the family or a piece of one; cutting a block into pieces never changes an
+// element's arithmetic (a matrix-core tile, a row's or a column's FMA chain,
+// one output's K-split sum are each computed whole by one unit), so a
+// problem's C stays bitwise that of the per-call kernel.
+//   U_TILE            one 16 x 16 matrix-core tile
+//   U_TILE2           two horizontally adjacent tiles (16 x 32)
+//   U_ROWS + r - 1    row strip, r = 1..4 rows x 64 columns
+//   U_COLS + c - 1    column strip, 64 rows x c = 1..4 columns
+//   U_KRED + c - 1    K-split block of 1 row x c = 1..4 columns
+// Few, small units keep the compute loop's code within the instruction
+// cache.
+enum { U_TILE = 0, U_TILE2 = 1, U_ROWS = 2, U_COLS = 6, U_KRED = 10, U_COUNT = 14 };
+
+template <int TA, int TB, bool CMEM>
+__device__ __forceinline__ void unit_body(int u, const SProb& P, int i0, int j0) {
+  switch (u) {
+    case U_TILE: StagedMfma<TA, TB, 1, 1, CMEM>::run(P, i0, j0); break;
+    case U_TILE2: StagedMfma<TA, TB, 1, 2, CMEM>::run(P, i0, j0); break;
+    case U_ROWS + 0: StagedRows<TA, TB, 1, CMEM>::run(P, i0, j0); break;
+    case U_ROWS + 1: StagedRows<TA, TB, 2, CMEM>::run(P, i0, j0); break;
+    case U_ROWS + 2: StagedRows<TA, TB, 3, CMEM>::run(P, i0, j0); break;
+    case U_ROWS + 3: StagedRows<TA, TB, 4, CMEM>::run(P, i0, j0); break;
+    case U_COLS + 0: StagedCols<TA, TB, 1, CMEM>::run(P, i0, j0); break;
+    case U_COLS + 1: StagedCols<TA, TB, 2, CMEM>::run(P, i0, j0); break;
+    case U_COLS + 2: StagedCols<TA, TB, 3, CMEM>::run(P, i0, j0); break;
+    case U_COLS + 3: StagedCols<TA, TB, 4, CMEM>::run(P, i0, j0); break;
+    case U_KRED + 0: StagedKred<TA, TB, 1, 1, CMEM>::run(P, i0, j0); break;
+    case U_KRED + 1: StagedKred<TA, TB, 1, 2, CMEM>::run(P, i0, j0); break;
+    case U_KRED + 2: StagedKred<TA, TB, 1, 3, CMEM>::run(P, i0, j0); break;
+    case U_KRED + 3: StagedKred<TA, TB, 1, 4, CMEM>::run(P, i0, j0); break;
+    default:
+      break;
+  }
+}
+
+// C is always staged when it is read (beta != 0), so the units never load
+// from memory.
+template <int TA, int TB>
+__device__ __forceinline__ void run_unit(int u, const SProb& P, int i0, int j0) {
+  unit_body<TA, TB, false>(u, P, i0, j0);
+}
+
+
+// ---- batched kernel: staged batches --------------------------------------
+//
+// Work-groups of eight wavefronts, two per CU (each owns half of the LDS,
+// so while one work-group waits for its copies the other computes).
+// Problems go to work-groups in windows of kWin consecutive problems: window
+// w to work-group w mod G, or, with a ticket counter, the first G windows so
+// and the rest to whichever work-group asks next (balancing the uneven
+// work).  Wavefront 0 packs a batch -- as many of the work-group's next
+// problems as fit into its staging buffer, one problem per lane, the
+// descriptors read a window ahead -- into one of two table sets.  Every
+// wavefront copies its share of the batch's A, B and (when beta != 0) C
+// spans verbatim into LDS with memory-to-LDS loads; after one wait,
+// wavefronts 1..7 take the batch's units one at a time from a shared counter
+// and run them from LDS, storing C, while wavefront 0 packs the next batch.  A barrier closes the iteration
+// because the buffer is refilled.  Problems that do not fit the buffer are
+// left to vbatched_direct_kernel; quick returns and status codes are handled
+// here.
+
+constexpr int kStage = 19312;        // floats of staging per work-group (>= one 80x80x80 problem)
+constexpr int kMaxBatch = 16;        // problems per batch
+constexpr int kMaxUnits = 128;       // units per batch
+constexpr int kWaves = 8;
+constexpr int kWin = 4;              // problems per descriptor window
+
+struct BatchProb {  // 64 bytes
+  float* C;
+  int la, lb, lc;  // float offsets into the staging buffer; lc < 0: C not staged
+  int m, n, k, lda, ldb, ldc;
+  float alpha, beta;
+  int trans;
+  int pad[2];
+};
+
+// One span copy of a batch: 16-byte-aligned source, staging offset (floats),
+// 16-byte units.
+struct CopyJob {
+  const float* src;
+  int dst, n4;
+};
+
+__shared__ __attribute__((aligned(16))) float g_stage[kStage];
+// Batch tables, double-buffered: wavefront 0 packs batch i+1 while batch i
+// is computed.
+__shared__ __attribute__((aligned(16))) BatchProb g_bprob[2][kMaxBatch];
+__shared__ uint32_t g_bunit[2][kMaxUnits];  // i0 | j0 << 8 | unit << 16 | problem slot << 24
+__shared__ int g_bnext[2];                  // the compute wavefronts' unit counters
+__shared__ CopyJob g_copy[2][3 * kMaxBatch];
+__shared__ int g_bhead[2][4];                    // problems, blocks, copies, more-to-come
+
+// Staged size of one problem: A, B and (beta != 0) C spans, each widened to
+// whole 16-byte units around it.
+struct PcGeom {
+  int a_sh, b_sh, c_sh;
+  int a_n4, b_n4, c_n4;
+  bool fits;
+};
+
+__device__ __forceinline__ PcGeom pc_geom(const Prob& P, int ta, int tb) {
+  PcGeom g;
+  const int64_t span_a = (int64_t)P.lda * ((ta ? P.m : P.k) - 1) + (ta ? P.k : P.m);
+  const int64_t span_b = (int64_t)P.ldb * ((tb ? P.k : P.n) - 1) + (tb ? P.n : P.k);
+  const int64_t span_c = P.beta != 0.0f ? (int64_t)P.ldc * (P.n - 1) + P.m : 0;
+  g.a_sh = (int)(((uintptr_t)P.A & 15) >> 2);
+  g.b_sh = (int)(((uintptr_t)P.B & 15) >> 2);
+  g.c_sh = (int)(((uintptr_t)P.C & 15) >> 2);
+  const int64_t a_n4 = (g.a_sh + span_a + 3) >> 2, b_n4 = (g.b_sh + span_b + 3) >> 2;
+  const int64_t c_n4 = span_c > 0 ? (g.c_sh + span_c + 3) >> 2 : 0;
+  g.fits = P.m <= kSuper && P.n <= kSuper && narrow(P) && 4 * (a_n4 + b_n4 + c_n4) <= kStage;
+  g.a_n4 = g.fits ? (int)a_n4 : 0;
+  g.b_n4 = g.fits ? (int)b_n4 : 0;
+  g.c_n4 = g.fits ? (int)c_n4 : 0;
+  return g;
+}
+
+// One 16-byte memory-to-LDS load: this lane's 16 bytes land at `base` + 16 *
+// lane (`base` is the same for the whole wavefront).
+__device__ __forceinline__ void copy16_lds(const float* g16, lds_f* base) {
+  typedef __attribute__((address_space(1))) const void gvoid;
+  typedef __attribute__((address_space(3))) void lvoid;
+  __builtin_amdgcn_global_load_lds((gvoid*)g16, (lvoid*)base, 16, 0, 0);
+}
+
+__device__ __forceinline__ int rdl(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+__device__ __forceinline__ uint32_t rdl(uint32_t v, int l) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, l);
+}
+__device__ __forceinline__ float rdlf(float v, int l) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+}
+
+// kWin descriptors (lane l < kWin holds problem base + l) and their plans.
+struct DescWindow {
+  uint32_t w[16];   // the iaat_problem words
+  uint32_t pl[16];  // the plan entry: block count, blocks
+};
+
+__device__ __forceinline__ void window_load(DescWindow& W, const VbArgs& a, int64_t base) {
+  const int64_t q = min(base + (lane() & (kWin - 1)), a.count - 1);
+  const uint32_t* src = reinterpret_cast<const uint32_t*>(a.probs + q);
+#pragma unroll
+  for (int i = 0; i < 16; ++i) W.w[i] = src[i];
+}
+
+__device__ __forceinline__ void window_load_plan(DescWindow& W, const PlanEntry* table) {
+  const int trans = (int)W.w[6];
+  const int m = min(max((int)W.w[7], 1), kSuper), n = min(max((int)W.w[8], 1), kSuper);
+  const u4* e = reinterpret_cast<const u4*>(table + plan_index(trans & 3, m, n));
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const u4 v = e[i];
+    W.pl[4 * i + 0] = v.x;
+    W.pl[4 * i + 1] = v.y;
+    W.pl[4 * i + 2] = v.z;
+    W.pl[4 * i + 3] = v.w;
+  }
+}
+
+// Visits the units of a plan held in registers (pl[0] = block count,
+// pl[1..15] = blocks): matrix-core grids as pairs of tiles along each row
+// (tiles wholly outside the problem dropped), strips in pieces of at most 4
+// rows or columns, K-split blocks row by row.  Fully unrolled, so the plan
+// words keep constant register indices.
+template <class F>
+__device__ __forceinline__ void for_each_unit(const uint32_t (&pl)[16], int m, int n, F&& f) {
+  const int nblk = (int)pl[0];
+#pragma unroll
+  for (int b = 0; b < kMaxBlocks; ++b) {
+    if (b < nblk) {
+      const uint32_t w = pl[1 + b];
+      const int kid = blk_kid(w), i0 = blk_i0(w), j0 = blk_j0(w);
+      if (kid < 9) {
+        const int tm = kid / 3 + 1, tn = kid % 3 + 1;
+        for (int ti = 0; ti < tm; ++ti) {
+          if (i0 + 16 * ti >= m) break;
+          for (int tj = 0; tj < tn; tj += 2) {
+            const int jj = j0 + 16 * tj;
+            if (jj >= n) break;
+            const bool pair = tj + 1 < tn && jj + 16 < n;
+            f(pair ? U_TILE2 : U_TILE, i0 + 16 * ti, jj);
+          }
+        }
+      } else if (kid < 17) {
+        const int mr = kid - 8;
+        for (int r = 0; r < mr; r += 4) f(U_ROWS + min(4, mr - r) - 1, i0 + r, j0);
+      } else if (kid < 25) {
+        const int nr = kid - 16;
+        for (int c = 0; c < nr; c += 4) f(U_COLS + min(4, nr - c) - 1, i0, j0 + c);
+      } else {
+        const int mr = (kid - 25) / 4 + 1, nr = (kid - 25) % 4 + 1;
+        for (int r = 0; r < mr; ++r) f(U_KRED + nr - 1, i0 + r, j0);
+      }
+    }
+  }
+}
+
+// The problem held by this lane / by lane `l` of a window.
+__device__ __forceinline__ Prob lane_prob(const DescWindow& W) {
+  const uint64_t A = ((uint64_t)W.w[1] << 32) | W.w[0];
+  const uint64_t B = ((uint64_t)W.w[3] << 32) | W.w[2];
+  const uint64_t C = ((uint64_t)W.w[5] << 32) | W.w[4];
+  return Prob{(const float*)A, (const float*)B, (float*)C, (int)W.w[7], (int)W.w[8], (int)W.w[9],
+              (int)W.w[10], (int)W.w[11], (int)W.w[12],
+              __builtin_bit_cast(float, W.w[13]) * __builtin_bit_cast(float, W.w[15]),
+              __builtin_bit_cast(float, W.w[14])};
+}
+
+__device__ __forceinline__ Prob lane_prob_of(const DescWindow& W, int l) {
+  const uint64_t A = ((uint64_t)rdl(W.w[1], l) << 32) | rdl(W.w[0], l);
+  const uint64_t B = ((uint64_t)rdl(W.w[3], l) << 32) | rdl(W.w[2], l);
+  const uint64_t C = ((uint64_t)rdl(W.w[5], l) << 32) | rdl(W.w[4], l);
+  return Prob{(const float*)A, (const float*)B, (float*)C, (int)rdl(W.w[7], l), (int)rdl(W.w[8], l),
+              (int)rdl(W.w[9], l), (int)rdl(W.w[10], l), (int)rdl(W.w[11], l),
+              (int)rdl(W.w[12], l),
+              __builtin_bit_cast(float, rdl(W.w[13], l)) * __builtin_bit_cast(float, rdl(W.w[15], l)),
+              __builtin_bit_cast(float, rdl(W.w[14], l))};
+}
+
+// Per-lane view of one problem of the current window (lane l < kWin holds
+// problem win*kWin + l): its class and, when it is staged, its copy jobs.
+enum { CLS_NONE = 0, CLS_QUICK = 1, CLS_STAGE = 2, CLS_DIRECT = 3 };
+
+struct LaneProb {
+  int cls, st, need, nbp;
+  PcGeom g;
+};
+
+__device__ __forceinline__ LaneProb classify(const DescWindow& W, bool valid_lane) {
+  LaneProb r{};
+  const Prob P = lane_prob(W);
+  const int trans = (int)W.w[6];
+  r.st = validate(trans, P.m, P.n, P.k, P.lda, P.ldb, P.ldc, P.alpha, P.A, P.B, P.C);
+  if (!valid_lane || r.st != 0 || P.m == 0 || P.n == 0) {
+    r.cls = CLS_NONE;
+  } else if (P.alpha == 0.0f || P.k == 0) {
+    r.cls = CLS_QUICK;
+  } else {
+    r.g = pc_geom(P, trans & 1, trans >> 1);
+    r.cls = r.g.fits ? CLS_STAGE : CLS_DIRECT;
+    r.need = r.g.fits ? 4 * (r.g.a_n4 + r.g.b_n4 + r.g.c_n4) : 0;
+    int nu = 0;
+    if (r.g.fits) for_each_unit(W.pl, P.m, P.n, [&](int, int, int) { ++nu; });
+    r.nbp = nu;
+  }
+  return r;
+}
+
+// Inclusive prefix sum over the first kWin lanes.
+__device__ __forceinline__ int scan16(int v) {
+  const int l = lane();
+#pragma unroll
+  for (int off = 1; off < kWin; off <<= 1) {
+    const int u = __shfl_up(v, off, 64);
+    if (l >= off) v += u;
+  }
+  return v;
+}
+
+// The window after `win` for this work-group: the next of its static share
+// (window w to work-group w mod G), or -- with a ticket counter -- the next
+// window not yet handed out (windows 0..G-1 go to work-groups 0..G-1 first).
+__device__ __forceinline__ int64_t next_window(const VbArgs& a, int64_t win, int64_t G) {
+  if (a.ticket == nullptr) return win + G;
+  uint32_t t = 0;
+  if (lane() == 0) t = atomicAdd(a.ticket, 1u);
+  return G + (int64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)t);
+}
+
+// Wavefront 0 packs the next batch: problems of this work-group's windows,
+// in order, while they fit.  All bookkeeping is per lane (one problem per
+// lane) plus prefix sums, then every taken lane writes its own table
+// entries; so the cost per batch does not grow with the number of problems.
+__device__ __forceinline__ void pack_batch(const VbArgs& a, int64_t G, int64_t nwin, int64_t& win,
+                                           int64_t& win1, int& i, DescWindow& W0, DescWindow& W1,
+                                           LaneProb& LP, int tb) {
+  const int l = lane();
+  int used = 0, np = 0, nb = 0, nc = 0;
+  bool more = true;
+  for (;;) {
+    if (i == kWin) {  // window done: W1 holds window win1's words, read one window ahead
+      win = win1;
+      if (win >= nwin) {
+        more = false;
+        break;
+      }
+      window_load_plan(W1, a.table);
+      W0 = W1;
+      i = 0;
+      LP = classify(W0, l < kWin && win * kWin + l < a.count);
+      win1 = next_window(a, win, G);
+      if (win1 < nwin) window_load(W1, a, win1 * kWin);
+    }
+    // candidates: lanes >= i that are staged
+    const bool cand = l >= i && l < kWin && LP.cls == CLS_STAGE;
+    const int c_need = scan16(cand ? LP.need : 0);
+    const int c_blk = scan16(cand ? LP.nbp : 0);
+    const int c_cnt = scan16(cand ? 1 : 0);
+    const bool fits = used + c_need <= kStage && nb + c_blk <= kMaxUnits && np + c_cnt <= kMaxBatch;
+    // first staged lane that does not fit ends this batch
+    const uint64_t stop = __ballot(cand && !fits) & ((1ull << kWin) - 1);
+    const int end = stop ? __builtin_ctzll(stop) : kWin;
+    const bool take = l >= i && l < end;  // consumed by this batch
+    const int64_t q = win * kWin + l;
+    if (take && LP.cls != CLS_NONE && a.status != nullptr) a.status[q] = 0;
+    if (take && LP.cls == CLS_NONE && l < kWin && q < a.count && a.status != nullptr) a.status[q] = LP.st;
+    // quick returns (beta * C), one after another
+    uint64_t qm = __ballot(take && LP.cls == CLS_QUICK);
+    while (qm) {
+      const int ql = __builtin_ctzll(qm);
+      qm &= qm - 1;
+      const Prob P = lane_prob_of(W0, ql);
+      scale_columns(P.C, P.m, P.n, P.ldc, P.beta, 0, 1);
+    }
+    if (take && LP.cls == CLS_STAGE) {
+      const int slot = np + c_cnt - 1;
+      const int off = used + c_need - LP.need;  // staging offset of this problem
+      const Prob P = lane_prob(W0);
+      const PcGeom& g = LP.g;
+      BatchProb& bp = g_bprob[tb][slot];
+      bp.C = P.C;
+      bp.la = off + g.a_sh;
+      bp.lb = off + 4 * g.a_n4 + g.b_sh;
+      bp.lc = g.c_n4 > 0 ? off + 4 * (g.a_n4 + g.b_n4) + g.c_sh : -1;
+      bp.m = P.m;
+      bp.n = P.n;
+      bp.k = P.k;
+      bp.lda = P.lda;
+      bp.ldb = P.ldb;
+      bp.ldc = P.ldc;
+      bp.alpha = P.alpha;
+      bp.beta = P.beta;
+      bp.trans = (int)W0.w[6];
+      CopyJob* cj = g_copy[tb] + 3 * slot;
+      cj[0] = CopyJob{P.A - g.a_sh, off, g.a_n4};
+      cj[1] = CopyJob{P.B - g.b_sh, off + 4 * g.a_n4, g.b_n4};
+      cj[2] = CopyJob{P.C - g.c_sh, off + 4 * (g.a_n4 + g.b_n4), g.c_n4};
+      int e = nb + c_blk - LP.nbp;
+      const uint32_t tag = (uint32_t)slot << 24;
+      for_each_unit(W0.pl, P.m, P.n, [&](int u, int i0, int j0) {
+        g_bunit[tb][e++] = (uint32_t)i0 | ((uint32_t)j0 << 8) | ((uint32_t)u << 16) | tag;
+      });
+    }
+    // totals of the taken lanes (lane end-1's prefix values; 0 if none)
+    const int last = end - 1;
+    const int t_need = last >= i ? __builtin_amdgcn_readlane(c_need, last) : 0;
+    const int t_blk = last >= i ? __builtin_amdgcn_readlane(c_blk, last) : 0;
+    const int t_cnt = last >= i ? __builtin_amdgcn_readlane(c_cnt, last) : 0;
+    used += t_need;
+    nb += t_blk;
+    np += t_cnt;
+    nc = 3 * np;
+    i = end;
+    if (end < kWin) break;  // a problem did not fit: this batch is full
+  }
+  if (l == 0) {
+    g_bhead[tb][0] = np;
+    g_bhead[tb][1] = nb;
+    g_bhead[tb][2] = nc;
+    g_bhead[tb][3] = more ? 1 : 0;
+    g_bnext[tb] = 0;
+  }
+}
+
+// Work-group barrier once this wavefront's staging copies have landed.
+__device__ __forceinline__ void staged_barrier() {
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
+}
+
+__device__ __forceinline__ uint32_t rfl(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+
+// A compute wavefront takes the batch's units one at a time from the shared
+// counter (the next one claimed before the current one runs, so the claim's
+// latency is hidden) and runs each from the staged operands.
+__device__ __forceinline__ void compute_batch(int t, lds_f* stage, int nb) {
+  int b = 0;
+  if (lane() == 0) b = atomicAdd(&g_bnext[t], 1);
+  b = uni(b);
+  while (b < nb) {
+    int bn = 0;
+    if (lane() == 0) bn = atomicAdd(&g_bnext[t], 1);
+    const uint32_t e = rfl(g_bunit[t][b]);
+    const int u = (int)((e >> 16) & 0xff), i0 = (int)(e & 0xff), j0 = (int)((e >> 8) & 0xff);
+    // the problem entry (64 bytes: C, la, lb, lc, m, n, k, lda, ldb, ldc,
+    // alpha, beta, trans): four 16-byte reads, made scalar
+    const u4* pe = reinterpret_cast<const u4*>(&g_bprob[t][e >> 24]);
+    const u4 w0 = pe[0], w1 = pe[1], w2 = pe[2], w3 = pe[3];
+    float* C = (float*)(((uint64_t)rfl(w0.y) << 32) | rfl(w0.x));
+    const int la = (int)rfl(w0.z), lb = (int)rfl(w0.w), lc = (int)rfl(w1.x);
+    const int m = (int)rfl(w1.y), n = (int)rfl(w1.z), k = (int)rfl(w1.w);
+    const int lda = (int)rfl(w2.x), ldb = (int)rfl(w2.y), ldc = (int)rfl(w2.z);
+    const float alpha = __builtin_bit_cast(float, rfl(w2.w)), beta = __builtin_bit_cast(float, rfl(w3.x));
+    const int trans = (int)rfl(w3.y);
+    const SProb P{stage + la, stage + lb, lc >= 0 ? stage + lc : nullptr, C, m, n, k, lda, ldb, ldc,
+                  ldc, alpha, beta};
+    switch (trans) {
+      case 0: run_unit<0, 0>(u, P, i0, j0); break;
+      case 1: run_unit<1, 0>(u, P, i0, j0); break;
+      case 2: run_unit<0, 1>(u, P, i0, j0); break;
+      default: run_unit<1, 1>(u, P, i0, j0); break;
+    }
+    b = uni(bn);
+  }
+}
+
+// Every wavefront issues its share of batch t's copies: job c is cut into
+// 64-unit chunks (one memory-to-LDS load instruction each); chunks are
+// numbered across jobs and chunk q goes to wavefront q mod 8.  Lane c holds
+// job c's entry (one LDS read).
+__device__ __forceinline__ void issue_copies(int t, int w, lds_f* stage) {
+  const int nc = uni(g_bhead[t][2]);
+  CopyJob my{};
+  if (lane() < nc) my = g_copy[t][lane()];
+  const uint64_t src_v = (uint64_t)my.src;
+  int qbase = 0;
+  for (int c = 0; c < nc; ++c) {
+    const int n4 = rdl(my.n4, c);
+    const int nch = (n4 + 63) >> 6;
+    if (n4 > 0) {
+      const uint64_t su = ((uint64_t)rdl((uint32_t)(src_v >> 32), c) << 32) | rdl((uint32_t)src_v, c);
+      const float* g16 = (const float*)su;
+      lds_f* dst = stage + rdl(my.dst, c);
+      for (int ch = (w - qbase) & (kWaves - 1); ch < nch; ch += kWaves) {
+        const int u = 64 * ch + lane();
+        if (u < n4) copy16_lds(g16 + 4 * u, dst + 256 * ch);
+      }
+    }
+    qbase += nch;
+  }
+}
+
+// Iteration t: every wavefront issues its share of batch t's copies; one
+// wait; wavefronts 1..7 compute batch t from LDS while wavefront 0 packs
+// batch t+1 into the other table set (its own copies have landed, so its
+// descriptor reads never wait behind them); a barrier closes the iteration
+// because the staging buffer is refilled.  Wavefront 0 and the others run
+// loops of their own with the same barriers, so the packer's state is not
+// live in the compute code.
+__device__ __forceinline__ void packer_loop(const VbArgs& a, lds_f* stage) {
+  const int64_t G = gridDim.x;
+  const int64_t nwin = (a.count + kWin - 1) / kWin;
+  int64_t win = blockIdx.x;  // this work-group's current window
+  DescWindow W0, W1;
+  int i = 0;
+  int64_t win1 = 0;  // the window after win (its words in W1)
+  window_load(W0, a, win * kWin);
+  window_load_plan(W0, a.table);
+  win1 = next_window(a, win, G);
+  if (win1 < nwin) window_load(W1, a, win1 * kWin);
+  LaneProb LP = classify(W0, lane() < kWin && win * kWin + lane() < a.count);
+  pack_batch(a, G, nwin, win, win1, i, W0, W1, LP, 0);
+  __syncthreads();  // batch 0's tables
+  for (int t = 0;; t ^= 1) {
+    const int more = uni(g_bhead[t][3]);
+    issue_copies(t, 0, stage);
+    staged_barrier();  // batch t has landed
+    if (more) pack_batch(a, G, nwin, win, win1, i, W0, W1, LP, t ^ 1);
+    if (!more) break;
+    __syncthreads();  // batch t computed (buffer free); batch t+1's tables visible
+  }
+}
+
+__device__ __forceinline__ void compute_loop(int w, lds_f* stage) {
+  __syncthreads();  // batch 0's tables
+  for (int t = 0;; t ^= 1) {
+    const int np = uni(g_bhead[t][0]);
+    const int nb = uni(g_bhead[t][1]);
+    const int more = uni(g_bhead[t][3]);
+    issue_copies(t, w, stage);
+    staged_barrier();  // batch t has landed
+    if (np > 0) compute_batch(t, stage, nb);
+    if (!more) break;
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 4)))
+void vbatched_f32_kernel(VbArgs a) {
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));  // wave-uniform
+  const int64_t nwin = (a.count + kWin - 1) / kWin;
+  if ((int64_t)blockIdx.x >= nwin) return;
+  lds_f* stage = (lds_f*)g_stage;
+  if (w == 0) packer_loop(a, stage);
+  else compute_loop(w, stage);
+}
+
+__device__ __forceinline__ bool load_problem(const VbArgs& a, int64_t q, Prob& P, int& trans,
+                                             int& st) {
+  const iaat_problem* d = a.probs + q;
+  trans = d->trans;
+  P.m = d->m;
+  P.n = d->n;
+  P.k = d->k;
+  P.lda = d->lda;
+  P.ldb = d->ldb;
+  P.ldc = d->ldc;
+  P.alpha = d->alpha * d->ab_scale;
+  P.beta = d->beta;
+  P.A = (const float*)d->A;
+  P.B = (const float*)d->B;
+  P.C = d->C;
+  st = validate(trans, P.m, P.n, P.k, P.lda, P.ldb, P.ldc, P.alpha, P.A, P.B, P.C);
+  return st == 0 && P.m > 0 && P.n > 0;
+}
+
+// Batched problems that do not fit the staging buffer.  Wavefront w of the
+// grid screens problems 64w .. 64w + 63, one per lane (valid, needs A*B, and
+// fails the same staging test as vbatched_f32_kernel, so every problem is
+// computed by exactly one of the two kernels), then computes the ones found,
+// one after another; most wavefronts find none and exit after one load.
+__global__ __launch_bounds__(64) void vbatched_direct_kernel(VbArgs a) {
+  const int64_t base = (int64_t)blockIdx.x * 64;
+  const int64_t q = base + lane();
+  bool need = false;
+  if (q < a.count) {
+    Prob P;
+    int trans, st;
+    if (load_problem(a, q, P, trans, st) && P.alpha != 0.0f && P.k != 0)
+      need = !pc_geom(P, trans & 1, trans >> 1).fits;
+  }
+  uint64_t mask = __ballot(need);
+  while (mask) {
+    const int l = __builtin_ctzll(mask);
+    mask &= mask - 1;
+    Prob P;
+    int trans, st;
+    load_problem(a, base + l, P, trans, st);
+    direct_problem(trans, P, a.table);
+  }
+}
+
+
+}  // namespace dev
+
+hipError_t launch_vbatched_f32_staged(const VbArgs& a, int grid, hipStream_t stream) {
+  hipLaunchKernelGGL(dev::vbatched_f32_kernel, dim3((unsigned)grid), dim3(512), 0, stream, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int dgrid = (int)((a.count + 63) / 64);  // one screening wavefront per 64 problems
+  hipLaunchKernelGGL(dev::vbatched_direct_kernel, dim3((unsigned)dgrid), dim3(64), 0, stream, a);
+  return hipGetLastError();
+}
+
+hipError_t vbatched_staged_occupancy(int* blocks_per_cu) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, dev::vbatched_f32_kernel, 512, 0);
+}
+
+}  // namespace iaat

@@ -37,8 +37,14 @@ hipError_t launch_gemm_f32_strided(const dev::Prob& P, int layout, const PlanEnt
                                    int64_t batch, hipStream_t stream);
 hipError_t launch_scale_f32_strided(float* C, int m, int n, int ldc, float beta, int64_t sc,
                                     int64_t batch, hipStream_t stream);
-hipError_t launch_vbatched_f32(const VbArgs& a, int grid, int direct_grid, hipStream_t stream);
-hipError_t vbatched_occupancy(int* blocks_per_cu, int* direct_per_cu);
+// The batched FP32 launch: a kernel clearing the ticket counter (when there
+// is one), then the persistent batched kernel (batched.hip) on `grid`
+// work-groups of 512 threads (two per CU) and its companion for problems too
+// large to stage.
+hipError_t launch_vbatched_f32(const VbArgs& a, int grid, hipStream_t stream);
+hipError_t launch_vbatched_f32_staged(const VbArgs& a, int grid, hipStream_t stream);
+hipError_t vbatched_occupancy(int* blocks_per_cu);
+hipError_t vbatched_staged_occupancy(int* blocks_per_cu);
 
 // Scratch of the allocation-free batched entry point (a file-scope device
 // array in kernels.hip, kScratchWords 32-bit words).  scratch_init(device)
