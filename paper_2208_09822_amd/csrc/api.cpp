@@ -156,6 +156,10 @@ int iaat_create(iaat_ctx_t* out, int device, const char* tile_table_path) {
     return hip_fail(e, "iaat_create: occupancy");
   }
   c->vb_grid = per_cu * c->num_cu;
+  if ((e = scratch_init(device)) != hipSuccess) {
+    free_ctx(c);
+    return hip_fail(e, "iaat_create: scratch address");
+  }
   const size_t tbytes = sizeof(PlanEntry) * c->table.size();
   if (hipMalloc(&c->table_dev, tbytes) != hipSuccess) {
     free_ctx(c);

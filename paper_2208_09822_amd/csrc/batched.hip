@@ -463,12 +463,16 @@ __device__ __forceinline__ void run_unit(int u, const SProb& P, int i0, int j0) 
 //
 // Work-groups of eight wavefronts, two per CU (each owns half of the LDS,
 // so while one work-group waits for its copies the other computes).
-// Problems go to work-groups in windows of kWin consecutive problems: window
-// w to work-group w mod G, or, with a ticket counter, the first G windows so
-// and the rest to whichever work-group asks next (balancing the uneven
-// work).  Wavefront 0 packs a batch -- as many of the work-group's next
-// problems as fit into its staging buffer, one problem per lane, the
-// descriptors read a window ahead -- into one of two table sets.  Every
+// Problems go to work-groups in windows of consecutive problems: first one
+// window of s0 problems per work-group, in order; then, with a ticket
+// counter, windows of shrinking size (guided self-scheduling: about the
+// remaining problems over twice the grid, 4..16) to whichever work-group
+// asks next, balancing the uneven work; without one, window w of size s0
+// to work-group w mod G.  Wavefront 0 packs a batch -- as many of the
+// work-group's next problems as fit into its staging buffer, one problem
+// per lane -- into one of two table sets.  The next window is fetched in
+// three dependent steps (claim, descriptors, plans), one step per batch,
+// so each step's latency hides behind a batch's copies.  Every
 // wavefront copies its share of the batch's A, B and (when beta != 0) C
 // spans verbatim into LDS with memory-to-LDS loads; after one wait,
 // wavefronts 1..7 take the batch's units one at a time from a shared counter
@@ -481,7 +485,7 @@ constexpr int kStage = 19312;        // floats of staging per work-group (>= one
 constexpr int kMaxBatch = 16;        // problems per batch
 constexpr int kMaxUnits = 128;       // units per batch
 constexpr int kWaves = 8;
-constexpr int kWin = 4;              // problems per descriptor window
+constexpr int kWin = 16;             // most problems per window (one per lane)
 
 struct BatchProb {  // 64 bytes
   float* C;
@@ -503,10 +507,13 @@ __shared__ __attribute__((aligned(16))) float g_stage[kStage];
 // Batch tables, double-buffered: wavefront 0 packs batch i+1 while batch i
 // is computed.
 __shared__ __attribute__((aligned(16))) BatchProb g_bprob[2][kMaxBatch];
-__shared__ uint32_t g_bunit[2][kMaxUnits];  // i0 | j0 << 8 | unit << 16 | problem slot << 24
+// i0 | j0 << 8 | unit << 16 | problem slot << 24; the longer units (all but
+// single tiles) from the front, the single tiles from the back, so the
+// compute wavefronts take the longest first and the batch ends evenly
+__shared__ uint32_t g_bunit[2][kMaxUnits];
 __shared__ int g_bnext[2];                  // the compute wavefronts' unit counters
 __shared__ CopyJob g_copy[2][3 * kMaxBatch];
-__shared__ int g_bhead[2][4];                    // problems, blocks, copies, more-to-come
+__shared__ int g_bhead[2][4];  // problems, units, long units, more-to-come
 
 // Staged size of one problem: A, B and (beta != 0) C spans, each widened to
 // whole 16-byte units around it.
@@ -549,17 +556,23 @@ __device__ __forceinline__ float rdlf(float v, int l) {
   return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
 }
 
-// kWin descriptors (lane l < kWin holds problem base + l) and their plans.
+// A window's descriptors (lane l < n holds problem base + l) and their plans.
 struct DescWindow {
   uint32_t w[16];   // the iaat_problem words
   uint32_t pl[16];  // the plan entry: block count, blocks
 };
 
-__device__ __forceinline__ void window_load(DescWindow& W, const VbArgs& a, int64_t base) {
-  const int64_t q = min(base + (lane() & (kWin - 1)), a.count - 1);
-  const uint32_t* src = reinterpret_cast<const uint32_t*>(a.probs + q);
+__device__ __forceinline__ void window_load(DescWindow& W, const VbArgs& a, int64_t base, int n) {
+  const int64_t q = base + min(lane() & (kWin - 1), n - 1);  // lanes >= n repeat the last one
+  const u4* src = reinterpret_cast<const u4*>(a.probs + q);
 #pragma unroll
-  for (int i = 0; i < 16; ++i) W.w[i] = src[i];
+  for (int i = 0; i < 4; ++i) {
+    const u4 v = src[i];
+    W.w[4 * i + 0] = v.x;
+    W.w[4 * i + 1] = v.y;
+    W.w[4 * i + 2] = v.z;
+    W.w[4 * i + 3] = v.w;
+  }
 }
 
 __device__ __forceinline__ void window_load_plan(DescWindow& W, const PlanEntry* table) {
@@ -641,8 +654,7 @@ __device__ __forceinline__ Prob lane_prob_of(const DescWindow& W, int l) {
 enum { CLS_NONE = 0, CLS_QUICK = 1, CLS_STAGE = 2, CLS_DIRECT = 3 };
 
 struct LaneProb {
-  int cls, st, need, nbp;
-  PcGeom g;
+  int cls, st, need, nbp, nlong;  // nbp units, nlong of them not single tiles
 };
 
 __device__ __forceinline__ LaneProb classify(const DescWindow& W, bool valid_lane) {
@@ -655,87 +667,154 @@ __device__ __forceinline__ LaneProb classify(const DescWindow& W, bool valid_lan
   } else if (P.alpha == 0.0f || P.k == 0) {
     r.cls = CLS_QUICK;
   } else {
-    r.g = pc_geom(P, trans & 1, trans >> 1);
-    r.cls = r.g.fits ? CLS_STAGE : CLS_DIRECT;
-    r.need = r.g.fits ? 4 * (r.g.a_n4 + r.g.b_n4 + r.g.c_n4) : 0;
-    int nu = 0;
-    if (r.g.fits) for_each_unit(W.pl, P.m, P.n, [&](int, int, int) { ++nu; });
+    const PcGeom g = pc_geom(P, trans & 1, trans >> 1);
+    r.cls = g.fits ? CLS_STAGE : CLS_DIRECT;
+    r.need = g.fits ? 4 * (g.a_n4 + g.b_n4 + g.c_n4) : 0;
+    int nu = 0, nl = 0;
+    if (g.fits)
+      for_each_unit(W.pl, P.m, P.n, [&](int u, int, int) {
+        ++nu;
+        nl += u != U_TILE;
+      });
     r.nbp = nu;
+    r.nlong = nl;
   }
   return r;
 }
 
-// Inclusive prefix sum over the first kWin lanes.
+// Inclusive prefix sum over the first kWin = 16 lanes (one DPP row: each
+// step adds the value `off` lanes down the row, 0 past its start).
 __device__ __forceinline__ int scan16(int v) {
-  const int l = lane();
-#pragma unroll
-  for (int off = 1; off < kWin; off <<= 1) {
-    const int u = __shfl_up(v, off, 64);
-    if (l >= off) v += u;
-  }
+  static_assert(kWin == 16, "one DPP row");
+  v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, true);  // row_shr:1
+  v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, true);  // row_shr:2
+  v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, true);  // row_shr:4
+  v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, true);  // row_shr:8
   return v;
 }
 
-// The window after `win` for this work-group: the next of its static share
-// (window w to work-group w mod G), or -- with a ticket counter -- the next
-// window not yet handed out (windows 0..G-1 go to work-groups 0..G-1 first).
-__device__ __forceinline__ int64_t next_window(const VbArgs& a, int64_t win, int64_t G) {
-  if (a.ticket == nullptr) return win + G;
-  uint32_t t = 0;
-  if (lane() == 0) t = atomicAdd(a.ticket, 1u);
-  return G + (int64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)t);
+// The packer's window stream.  `cur` is the window being packed (lanes
+// i.. of it still to take); `nxt` the one after it, fetched a step per batch:
+// hop 1 claims it (the ticket's old value arrives with the next wait),
+// hop 2 loads its descriptors, hop 3 its plans.
+struct Windows {
+  DescWindow cur, nxt;
+  LaneProb lp;         // per-lane class of cur's problems
+  int64_t base0;       // cur: problems base0 .. base0 + n0 - 1
+  int n0, i;
+  int64_t base1;       // nxt
+  int n1, s1;          // nxt's size; the size asked for at the claim
+  int hop;             // steps of nxt done (3: ready)
+  bool end;            // no window after cur
+  uint32_t tk;         // lane 0: the ticket's value before the claim
+  uint32_t t_last;     // the last ticket value seen (a progress estimate)
+  int64_t sbase;       // without a ticket: the last static window
+};
+
+struct WinShape {
+  int64_t count, G, s0;
+};
+
+__device__ __forceinline__ WinShape win_shape(const VbArgs& a) {
+  WinShape z;
+  z.count = a.count;
+  z.G = gridDim.x;
+  z.s0 = min<int64_t>(kWin, max<int64_t>(1, a.count / (2 * z.G)));
+  return z;
+}
+
+// One step of fetching nxt (each needs the previous step's loads).
+__device__ __forceinline__ void win_step(Windows& S, const VbArgs& a, const WinShape& z) {
+  if (S.end) return;
+  if (S.hop == 0) {  // claim
+    if (a.ticket != nullptr) {
+      const int64_t rem = z.count - (z.G * z.s0 + (int64_t)S.t_last);
+      S.s1 = (int)min<int64_t>(kWin, max<int64_t>(4, rem / (2 * z.G)));
+      if (lane() == 0) S.tk = atomicAdd(a.ticket, (uint32_t)S.s1);
+    }
+    S.hop = 1;
+  } else if (S.hop == 1) {  // descriptors
+    int64_t base;
+    if (a.ticket != nullptr) {
+      S.t_last = (uint32_t)__builtin_amdgcn_readfirstlane((int)S.tk);
+      base = z.G * z.s0 + (int64_t)S.t_last;
+    } else {
+      S.sbase += z.G * z.s0;
+      base = S.sbase;
+      S.s1 = (int)z.s0;
+    }
+    if (base >= z.count) {
+      S.end = true;
+      return;
+    }
+    S.base1 = base;
+    S.n1 = (int)min<int64_t>(S.s1, z.count - base);
+    window_load(S.nxt, a, base, S.n1);
+    S.hop = 2;
+  } else if (S.hop == 2) {  // plans
+    window_load_plan(S.nxt, a.table);
+    S.hop = 3;
+  }
+}
+
+// cur := nxt (finishing its fetch if a window went faster than three
+// batches), classified, and the claim of the one after it.  False at the end.
+__device__ __forceinline__ bool win_advance(Windows& S, const VbArgs& a, const WinShape& z) {
+  while (!S.end && S.hop < 3) win_step(S, a, z);
+  if (S.end) return false;
+  S.cur = S.nxt;
+  S.base0 = S.base1;
+  S.n0 = S.n1;
+  S.i = 0;
+  S.lp = classify(S.cur, lane() < S.n0);
+  S.hop = 0;
+  win_step(S, a, z);
+  return true;
 }
 
 // Wavefront 0 packs the next batch: problems of this work-group's windows,
 // in order, while they fit.  All bookkeeping is per lane (one problem per
 // lane) plus prefix sums, then every taken lane writes its own table
 // entries; so the cost per batch does not grow with the number of problems.
-__device__ __forceinline__ void pack_batch(const VbArgs& a, int64_t G, int64_t nwin, int64_t& win,
-                                           int64_t& win1, int& i, DescWindow& W0, DescWindow& W1,
-                                           LaneProb& LP, int tb) {
+__device__ __forceinline__ void pack_batch(const VbArgs& a, const WinShape& z, Windows& S, int tb) {
   const int l = lane();
-  int used = 0, np = 0, nb = 0, nc = 0;
+  int used = 0, np = 0, nb = 0, nlong = 0;
   bool more = true;
+  win_step(S, a, z);  // one fetch step per batch
   for (;;) {
-    if (i == kWin) {  // window done: W1 holds window win1's words, read one window ahead
-      win = win1;
-      if (win >= nwin) {
-        more = false;
-        break;
-      }
-      window_load_plan(W1, a.table);
-      W0 = W1;
-      i = 0;
-      LP = classify(W0, l < kWin && win * kWin + l < a.count);
-      win1 = next_window(a, win, G);
-      if (win1 < nwin) window_load(W1, a, win1 * kWin);
+    if (S.i == S.n0 && !win_advance(S, a, z)) {
+      more = false;
+      break;
     }
+    const int i = S.i;
+    const LaneProb& LP = S.lp;
     // candidates: lanes >= i that are staged
-    const bool cand = l >= i && l < kWin && LP.cls == CLS_STAGE;
+    const bool cand = l >= i && LP.cls == CLS_STAGE;
     const int c_need = scan16(cand ? LP.need : 0);
     const int c_blk = scan16(cand ? LP.nbp : 0);
+    const int c_long = scan16(cand ? LP.nlong : 0);
     const int c_cnt = scan16(cand ? 1 : 0);
     const bool fits = used + c_need <= kStage && nb + c_blk <= kMaxUnits && np + c_cnt <= kMaxBatch;
-    // first staged lane that does not fit ends this batch
+    // the first staged lane that does not fit ends this batch
     const uint64_t stop = __ballot(cand && !fits) & ((1ull << kWin) - 1);
-    const int end = stop ? __builtin_ctzll(stop) : kWin;
+    const int end = stop ? __builtin_ctzll(stop) : S.n0;
     const bool take = l >= i && l < end;  // consumed by this batch
-    const int64_t q = win * kWin + l;
-    if (take && LP.cls != CLS_NONE && a.status != nullptr) a.status[q] = 0;
-    if (take && LP.cls == CLS_NONE && l < kWin && q < a.count && a.status != nullptr) a.status[q] = LP.st;
+    const int64_t q = S.base0 + l;
+    if (take && a.status != nullptr) a.status[q] = LP.cls == CLS_NONE ? LP.st : 0;
     // quick returns (beta * C), one after another
     uint64_t qm = __ballot(take && LP.cls == CLS_QUICK);
     while (qm) {
       const int ql = __builtin_ctzll(qm);
       qm &= qm - 1;
-      const Prob P = lane_prob_of(W0, ql);
+      const Prob P = lane_prob_of(S.cur, ql);
       scale_columns(P.C, P.m, P.n, P.ldc, P.beta, 0, 1);
     }
     if (take && LP.cls == CLS_STAGE) {
       const int slot = np + c_cnt - 1;
       const int off = used + c_need - LP.need;  // staging offset of this problem
-      const Prob P = lane_prob(W0);
-      const PcGeom& g = LP.g;
+      const Prob P = lane_prob(S.cur);
+      const int trans = (int)S.cur.w[6];
+      const PcGeom g = pc_geom(P, trans & 1, trans >> 1);  // recomputed: fewer live registers
       BatchProb& bp = g_bprob[tb][slot];
       bp.C = P.C;
       bp.la = off + g.a_sh;
@@ -749,33 +828,36 @@ __device__ __forceinline__ void pack_batch(const VbArgs& a, int64_t G, int64_t n
       bp.ldc = P.ldc;
       bp.alpha = P.alpha;
       bp.beta = P.beta;
-      bp.trans = (int)W0.w[6];
+      bp.trans = trans;
       CopyJob* cj = g_copy[tb] + 3 * slot;
       cj[0] = CopyJob{P.A - g.a_sh, off, g.a_n4};
       cj[1] = CopyJob{P.B - g.b_sh, off + 4 * g.a_n4, g.b_n4};
       cj[2] = CopyJob{P.C - g.c_sh, off + 4 * (g.a_n4 + g.b_n4), g.c_n4};
-      int e = nb + c_blk - LP.nbp;
+      // long units at the front, single tiles at the back
+      int el = nlong + c_long - LP.nlong;
+      int es = kMaxUnits - 1 - ((nb - nlong) + (c_blk - c_long) - (LP.nbp - LP.nlong));
       const uint32_t tag = (uint32_t)slot << 24;
-      for_each_unit(W0.pl, P.m, P.n, [&](int u, int i0, int j0) {
-        g_bunit[tb][e++] = (uint32_t)i0 | ((uint32_t)j0 << 8) | ((uint32_t)u << 16) | tag;
+      for_each_unit(S.cur.pl, P.m, P.n, [&](int u, int i0, int j0) {
+        const uint32_t e = (uint32_t)i0 | ((uint32_t)j0 << 8) | ((uint32_t)u << 16) | tag;
+        if (u != U_TILE) g_bunit[tb][el++] = e;
+        else g_bunit[tb][es--] = e;
       });
     }
     // totals of the taken lanes (lane end-1's prefix values; 0 if none)
     const int last = end - 1;
-    const int t_need = last >= i ? __builtin_amdgcn_readlane(c_need, last) : 0;
-    const int t_blk = last >= i ? __builtin_amdgcn_readlane(c_blk, last) : 0;
-    const int t_cnt = last >= i ? __builtin_amdgcn_readlane(c_cnt, last) : 0;
-    used += t_need;
-    nb += t_blk;
-    np += t_cnt;
-    nc = 3 * np;
-    i = end;
-    if (end < kWin) break;  // a problem did not fit: this batch is full
+    if (last >= i) {
+      used += __builtin_amdgcn_readlane(c_need, last);
+      nb += __builtin_amdgcn_readlane(c_blk, last);
+      nlong += __builtin_amdgcn_readlane(c_long, last);
+      np += __builtin_amdgcn_readlane(c_cnt, last);
+    }
+    S.i = end;
+    if (end < S.n0) break;  // a problem did not fit: this batch is full
   }
   if (l == 0) {
     g_bhead[tb][0] = np;
     g_bhead[tb][1] = nb;
-    g_bhead[tb][2] = nc;
+    g_bhead[tb][2] = nlong;
     g_bhead[tb][3] = more ? 1 : 0;
     g_bnext[tb] = 0;
   }
@@ -794,14 +876,15 @@ __device__ __forceinline__ uint32_t rfl(uint32_t v) {
 // A compute wavefront takes the batch's units one at a time from the shared
 // counter (the next one claimed before the current one runs, so the claim's
 // latency is hidden) and runs each from the staged operands.
-__device__ __forceinline__ void compute_batch(int t, lds_f* stage, int nb) {
+__device__ __forceinline__ void compute_batch(int t, lds_f* stage, int nb, int nlong) {
+  const int gap = kMaxUnits - nb;  // unit b >= nlong sits at b + gap
   int b = 0;
   if (lane() == 0) b = atomicAdd(&g_bnext[t], 1);
   b = uni(b);
   while (b < nb) {
     int bn = 0;
     if (lane() == 0) bn = atomicAdd(&g_bnext[t], 1);
-    const uint32_t e = rfl(g_bunit[t][b]);
+    const uint32_t e = rfl(g_bunit[t][b < nlong ? b : b + gap]);
     const int u = (int)((e >> 16) & 0xff), i0 = (int)(e & 0xff), j0 = (int)((e >> 8) & 0xff);
     // the problem entry (64 bytes: C, la, lb, lc, m, n, k, lda, ldb, ldc,
     // alpha, beta, trans): four 16-byte reads, made scalar
@@ -830,7 +913,7 @@ __device__ __forceinline__ void compute_batch(int t, lds_f* stage, int nb) {
 // numbered across jobs and chunk q goes to wavefront q mod 8.  Lane c holds
 // job c's entry (one LDS read).
 __device__ __forceinline__ void issue_copies(int t, int w, lds_f* stage) {
-  const int nc = uni(g_bhead[t][2]);
+  const int nc = 3 * uni(g_bhead[t][0]);  // three copy jobs per problem
   CopyJob my{};
   if (lane() < nc) my = g_copy[t][lane()];
   const uint64_t src_v = (uint64_t)my.src;
@@ -859,24 +942,27 @@ __device__ __forceinline__ void issue_copies(int t, int w, lds_f* stage) {
 // loops of their own with the same barriers, so the packer's state is not
 // live in the compute code.
 __device__ __forceinline__ void packer_loop(const VbArgs& a, lds_f* stage) {
-  const int64_t G = gridDim.x;
-  const int64_t nwin = (a.count + kWin - 1) / kWin;
-  int64_t win = blockIdx.x;  // this work-group's current window
-  DescWindow W0, W1;
-  int i = 0;
-  int64_t win1 = 0;  // the window after win (its words in W1)
-  window_load(W0, a, win * kWin);
-  window_load_plan(W0, a.table);
-  win1 = next_window(a, win, G);
-  if (win1 < nwin) window_load(W1, a, win1 * kWin);
-  LaneProb LP = classify(W0, lane() < kWin && win * kWin + lane() < a.count);
-  pack_batch(a, G, nwin, win, win1, i, W0, W1, LP, 0);
+  const WinShape z = win_shape(a);
+  Windows S;
+  S.end = false;
+  S.t_last = 0;
+  S.tk = 0;
+  S.s1 = (int)z.s0;
+  // this work-group's first window, fetched at once
+  S.sbase = (int64_t)blockIdx.x * z.s0;
+  S.base1 = S.sbase;
+  S.n1 = (int)min<int64_t>(z.s0, z.count - S.sbase);
+  window_load(S.nxt, a, S.base1, S.n1);
+  window_load_plan(S.nxt, a.table);
+  S.hop = 3;
+  win_advance(S, a, z);
+  pack_batch(a, z, S, 0);
   __syncthreads();  // batch 0's tables
   for (int t = 0;; t ^= 1) {
     const int more = uni(g_bhead[t][3]);
     issue_copies(t, 0, stage);
     staged_barrier();  // batch t has landed
-    if (more) pack_batch(a, G, nwin, win, win1, i, W0, W1, LP, t ^ 1);
+    if (more) pack_batch(a, z, S, t ^ 1);
     if (!more) break;
     __syncthreads();  // batch t computed (buffer free); batch t+1's tables visible
   }
@@ -888,9 +974,10 @@ __device__ __forceinline__ void compute_loop(int w, lds_f* stage) {
     const int np = uni(g_bhead[t][0]);
     const int nb = uni(g_bhead[t][1]);
     const int more = uni(g_bhead[t][3]);
+    const int nlong = uni(g_bhead[t][2]);
     issue_copies(t, w, stage);
     staged_barrier();  // batch t has landed
-    if (np > 0) compute_batch(t, stage, nb);
+    if (np > 0) compute_batch(t, stage, nb, nlong);
     if (!more) break;
     __syncthreads();
   }
@@ -899,8 +986,7 @@ __device__ __forceinline__ void compute_loop(int w, lds_f* stage) {
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 4)))
 void vbatched_f32_kernel(VbArgs a) {
   const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));  // wave-uniform
-  const int64_t nwin = (a.count + kWin - 1) / kWin;
-  if ((int64_t)blockIdx.x >= nwin) return;
+  if ((int64_t)blockIdx.x * win_shape(a).s0 >= a.count) return;
   lds_f* stage = (lds_f*)g_stage;
   if (w == 0) packer_loop(a, stage);
   else compute_loop(w, stage);
