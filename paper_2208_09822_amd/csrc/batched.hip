@@ -589,41 +589,57 @@ __device__ __forceinline__ void window_load_plan(DescWindow& W, const PlanEntry*
   }
 }
 
-// Visits the units of a plan held in registers (pl[0] = block count,
-// pl[1..15] = blocks): matrix-core grids as pairs of tiles along each row
-// (tiles wholly outside the problem dropped), strips in pieces of at most 4
-// rows or columns, K-split blocks row by row.  Fully unrolled, so the plan
-// words keep constant register indices.
-template <class F>
-__device__ __forceinline__ void for_each_unit(const uint32_t (&pl)[16], int m, int n, F&& f) {
-  const int nblk = (int)pl[0];
-#pragma unroll
-  for (int b = 0; b < kMaxBlocks; ++b) {
-    if (b < nblk) {
-      const uint32_t w = pl[1 + b];
-      const int kid = blk_kid(w), i0 = blk_i0(w), j0 = blk_j0(w);
-      if (kid < 9) {
-        const int tm = kid / 3 + 1, tn = kid % 3 + 1;
-        for (int ti = 0; ti < tm; ++ti) {
-          if (i0 + 16 * ti >= m) break;
-          for (int tj = 0; tj < tn; tj += 2) {
-            const int jj = j0 + 16 * tj;
-            if (jj >= n) break;
-            const bool pair = tj + 1 < tn && jj + 16 < n;
-            f(pair ? U_TILE2 : U_TILE, i0 + 16 * ti, jj);
-          }
-        }
-      } else if (kid < 17) {
-        const int mr = kid - 8;
-        for (int r = 0; r < mr; r += 4) f(U_ROWS + min(4, mr - r) - 1, i0 + r, j0);
-      } else if (kid < 25) {
-        const int nr = kid - 16;
-        for (int c = 0; c < nr; c += 4) f(U_COLS + min(4, nr - c) - 1, i0, j0 + c);
-      } else {
-        const int mr = (kid - 25) / 4 + 1, nr = (kid - 25) % 4 + 1;
-        for (int r = 0; r < mr; ++r) f(U_KRED + nr - 1, i0 + r, j0);
-      }
+// The units of one plan block: matrix-core grids as pairs of tiles along
+// each row, a row's odd tile alone (tiles wholly outside the problem
+// dropped), strips in pieces of at most 4 rows or columns, K-split blocks
+// row by row.  block_units counts them in closed form -- `nl` long units
+// (all but single tiles) and `ns` single tiles -- and emit_block writes
+// them, long ones at ascending indices from `el`, single tiles at
+// descending indices from `es`; both follow the same decomposition, so a
+// block always writes exactly the units counted for it.
+__device__ __forceinline__ void block_units(uint32_t w, int m, int n, int& nl, int& ns) {
+  const int kid = blk_kid(w), i0 = blk_i0(w), j0 = blk_j0(w);
+  nl = 0;
+  ns = 0;
+  if (kid < 9) {
+    const int tm = kid / 3 + 1, tn = kid % 3 + 1;
+    const int ri = min(tm, max(0, (m - i0 + 15) >> 4));  // tile rows inside the problem
+    const int ci = min(tn, max(0, (n - j0 + 15) >> 4));  // tile columns inside
+    nl = ri * (ci >> 1);
+    ns = ri * (ci & 1);
+  } else if (kid < 17) {
+    nl = (kid - 8 + 3) >> 2;
+  } else if (kid < 25) {
+    nl = (kid - 16 + 3) >> 2;
+  } else {
+    nl = (kid - 25) / 4 + 1;
+  }
+}
+
+__device__ __forceinline__ void emit_block(uint32_t* units, uint32_t w, int m, int n, uint32_t tag,
+                                           int el, int es) {
+  const int kid = blk_kid(w), i0 = blk_i0(w), j0 = blk_j0(w);
+  auto put = [&](int idx, int u, int i, int j) {
+    units[idx] = (uint32_t)i | ((uint32_t)j << 8) | ((uint32_t)u << 16) | tag;
+  };
+  if (kid < 9) {
+    const int tm = kid / 3 + 1, tn = kid % 3 + 1;
+    const int ri = min(tm, max(0, (m - i0 + 15) >> 4));
+    const int ci = min(tn, max(0, (n - j0 + 15) >> 4));
+    const int pairs = ci >> 1;
+    for (int ti = 0; ti < ri; ++ti) {
+      for (int c = 0; c < pairs; ++c) put(el++, U_TILE2, i0 + 16 * ti, j0 + 32 * c);
+      if (ci & 1) put(es--, U_TILE, i0 + 16 * ti, j0 + 32 * pairs);
     }
+  } else if (kid < 17) {
+    const int mr = kid - 8;
+    for (int r = 0; r < mr; r += 4) put(el++, U_ROWS + min(4, mr - r) - 1, i0 + r, j0);
+  } else if (kid < 25) {
+    const int nr = kid - 16;
+    for (int c = 0; c < nr; c += 4) put(el++, U_COLS + min(4, nr - c) - 1, i0, j0 + c);
+  } else {
+    const int mr = (kid - 25) / 4 + 1, nr = (kid - 25) % 4 + 1;
+    for (int r = 0; r < mr; ++r) put(el++, U_KRED + nr - 1, i0 + r, j0);
   }
 }
 
@@ -671,11 +687,17 @@ __device__ __forceinline__ LaneProb classify(const DescWindow& W, bool valid_lan
     r.cls = g.fits ? CLS_STAGE : CLS_DIRECT;
     r.need = g.fits ? 4 * (g.a_n4 + g.b_n4 + g.c_n4) : 0;
     int nu = 0, nl = 0;
-    if (g.fits)
-      for_each_unit(W.pl, P.m, P.n, [&](int u, int, int) {
-        ++nu;
-        nl += u != U_TILE;
-      });
+    if (g.fits) {
+#pragma unroll
+      for (int b = 0; b < kMaxBlocks; ++b) {
+        if (b < (int)W.pl[0]) {
+          int bl, bs;
+          block_units(W.pl[1 + b], P.m, P.n, bl, bs);
+          nu += bl + bs;
+          nl += bl;
+        }
+      }
+    }
     r.nbp = nu;
     r.nlong = nl;
   }
@@ -772,6 +794,50 @@ __device__ __forceinline__ bool win_advance(Windows& S, const VbArgs& a, const W
   return true;
 }
 
+__device__ __forceinline__ uint32_t bperm(int src_lane, uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_ds_bpermute(src_lane << 2, (int)v);
+}
+
+// Writes the units of the taken staged problems of the current window:
+// long units of a problem from index `el` up, its single tiles from `es`
+// down (per-lane values of the problem's lane).  Lane-per-block: four
+// problems a round, lane 16q + b holding block b of the round's q-th
+// problem (its plan words gathered from the problem's lane), with the
+// block's offsets inside its problem from a 16-lane prefix sum.
+__device__ __forceinline__ void emit_units(const Windows& S, const LaneProb& LP, bool take, int tb,
+                                           int slot, int el, int es) {
+  const int l = lane();
+  uint32_t sm = (uint32_t)__ballot(take && LP.cls == CLS_STAGE) & 0xffffu;
+  const uint32_t tag = (uint32_t)slot << 24;
+  const int q = l >> 4, b = l & 15;
+  while (sm) {
+    // the round's problems: lanes 16q.. take the q-th next set lane of sm
+    uint32_t v = sm;
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+      if (q > r) v &= v - 1;
+    const int p = v ? __builtin_ctz(v) : -1;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) sm &= sm - 1;
+    const int src = p < 0 ? 0 : p;
+    uint32_t w = 0;
+#pragma unroll
+    for (int j = 1; j < 16; ++j) {
+      const uint32_t x = bperm(src, S.cur.pl[j]);
+      if (b == j - 1) w = x;
+    }
+    const int nblk = (int)bperm(src, S.cur.pl[0]);
+    const int m = (int)bperm(src, S.cur.w[7]), n = (int)bperm(src, S.cur.w[8]);
+    const int pel = (int)bperm(src, (uint32_t)el), pes = (int)bperm(src, (uint32_t)es);
+    const uint32_t ptag = bperm(src, tag);
+    const bool valid = p >= 0 && b < nblk;
+    int bl = 0, bs = 0;
+    if (valid) block_units(w, m, n, bl, bs);
+    const int ol = scan16(bl) - bl, os = scan16(bs) - bs;  // earlier blocks of the problem
+    if (valid) emit_block(g_bunit[tb], w, m, n, ptag, pel + ol, pes - os);
+  }
+}
+
 // Wavefront 0 packs the next batch: problems of this work-group's windows,
 // in order, while they fit.  All bookkeeping is per lane (one problem per
 // lane) plus prefix sums, then every taken lane writes its own table
@@ -833,16 +899,9 @@ __device__ __forceinline__ void pack_batch(const VbArgs& a, const WinShape& z, W
       cj[0] = CopyJob{P.A - g.a_sh, off, g.a_n4};
       cj[1] = CopyJob{P.B - g.b_sh, off + 4 * g.a_n4, g.b_n4};
       cj[2] = CopyJob{P.C - g.c_sh, off + 4 * (g.a_n4 + g.b_n4), g.c_n4};
-      // long units at the front, single tiles at the back
-      int el = nlong + c_long - LP.nlong;
-      int es = kMaxUnits - 1 - ((nb - nlong) + (c_blk - c_long) - (LP.nbp - LP.nlong));
-      const uint32_t tag = (uint32_t)slot << 24;
-      for_each_unit(S.cur.pl, P.m, P.n, [&](int u, int i0, int j0) {
-        const uint32_t e = (uint32_t)i0 | ((uint32_t)j0 << 8) | ((uint32_t)u << 16) | tag;
-        if (u != U_TILE) g_bunit[tb][el++] = e;
-        else g_bunit[tb][es--] = e;
-      });
     }
+    emit_units(S, LP, take, tb, np + c_cnt - 1, nlong + c_long - LP.nlong,
+               kMaxUnits - 1 - ((nb - nlong) + (c_blk - c_long) - (LP.nbp - LP.nlong)));
     // totals of the taken lanes (lane end-1's prefix values; 0 if none)
     const int last = end - 1;
     if (last >= i) {
