@@ -9,8 +9,9 @@ code with it: no kernels, headers, helpers, tables or generators.
 Contents
   gemm_f64.c   FP64 triple-loop GEMM (Section I statement, Table 1 note for the
                layouts) for FP32 inputs, and the same loop with FP64 operands
-               (DGEMM, Table 1 row D), and the complex loop (CGEMM, row C),
-               built with gcc into ``_build/liboracle.so``.
+               (DGEMM, Table 1 row D), and the complex loops (CGEMM, row C,
+               FP32 storage; ZGEMM, row Z, FP64 storage), built with gcc
+               into ``_build/liboracle.so``.
   quant.py     BF16 / FP16 / FP8-E4M3 rounding from the format definitions,
                the split-BF16 pair, the power-of-two FP8 scale.
   tiler_ref.py A reading of the SGEMM_NN tile algorithm (Section V-A,
@@ -66,6 +67,8 @@ def _load():
             lib.oracle_cgemm.argtypes = [i32, i32, i64, i64, i64, dbl, dbl, vp, i64, vp, i64,
                                          dbl, dbl, vp, i64, vp, i64]
             lib.oracle_cgemm.restype = None
+            lib.oracle_zgemm.argtypes = lib.oracle_cgemm.argtypes
+            lib.oracle_zgemm.restype = None
             lib.oracle_gemm_batch.argtypes = [i64] + [vp] * 15 + [i32]
             lib.oracle_gemm_batch.restype = dbl
             _lib = lib
@@ -132,6 +135,22 @@ def cgemm(ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C0, ldc):
     al, be = complex(alpha), complex(beta)
     if m > 0 and n > 0:
         lib.oracle_cgemm(int(ta), int(tb), m, n, k, al.real, al.imag, _ptr(a), lda, _ptr(b), ldb,
+                         be.real, be.imag, _ptr(c), ldc, _ptr(out), max(m, 1))
+    return out[:n, :m].T.copy()
+
+
+def zgemm(ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C0, ldc):
+    """ZGEMM (Table 1, row Z; Eq. 2's complex product): complex128 operands
+    (numpy arrays of the stored matrices, column-major, flat), complex
+    alpha/beta; complex128 m x n result."""
+    lib = _load()
+    out = np.zeros((max(n, 1), max(m, 1)), dtype=np.complex128)
+    a = None if A is None else np.ascontiguousarray(A, dtype=np.complex128)
+    b = None if B is None else np.ascontiguousarray(B, dtype=np.complex128)
+    c = None if C0 is None else np.ascontiguousarray(C0, dtype=np.complex128)
+    al, be = complex(alpha), complex(beta)
+    if m > 0 and n > 0:
+        lib.oracle_zgemm(int(ta), int(tb), m, n, k, al.real, al.imag, _ptr(a), lda, _ptr(b), ldb,
                          be.real, be.imag, _ptr(c), ldc, _ptr(out), max(m, 1))
     return out[:n, :m].T.copy()
 

@@ -181,6 +181,43 @@ void oracle_cgemm(int ta, int tb, int64_t m, int64_t n, int64_t k,
     }
 }
 
+/* ZGEMM (Table 1, row Z): complex operands stored as interleaved FP64
+ * (re, im) pairs; complex alpha, beta; op(X) = X or X^T (no conjugation).
+ * Each complex product expands as in Eq. 2 into four real products, the
+ * real part (ar*br - ai*bi) and the imaginary part (ar*bi + ai*br), summed
+ * over p in increasing order in FP64.  out is interleaved FP64.  C0 is not
+ * read when beta == 0; A and B are not read when alpha == 0 or k == 0. */
+void oracle_zgemm(int ta, int tb, int64_t m, int64_t n, int64_t k,
+                  double alpha_re, double alpha_im, const double* A, int64_t lda,
+                  const double* B, int64_t ldb, double beta_re, double beta_im,
+                  const double* C0, int64_t ldc, double* out, int64_t ldo)
+{
+    for (int64_t j = 0; j < n; ++j) {
+        for (int64_t i = 0; i < m; ++i) {
+            double sr = 0.0, si = 0.0;
+            if ((alpha_re != 0.0 || alpha_im != 0.0) && k > 0) {
+                for (int64_t p = 0; p < k; ++p) {
+                    int64_t ia = ta ? p + i * lda : i + p * lda;
+                    int64_t ib = tb ? j + p * ldb : p + j * ldb;
+                    double ar = A[2 * ia], ai = A[2 * ia + 1];
+                    double br = B[2 * ib], bi = B[2 * ib + 1];
+                    sr += ar * br - ai * bi;
+                    si += ar * bi + ai * br;
+                }
+            }
+            double rr = alpha_re * sr - alpha_im * si;
+            double ri = alpha_re * si + alpha_im * sr;
+            if (beta_re != 0.0 || beta_im != 0.0) {
+                double cr = C0[2 * (i + j * ldc)], ci = C0[2 * (i + j * ldc) + 1];
+                rr += beta_re * cr - beta_im * ci;
+                ri += beta_re * ci + beta_im * cr;
+            }
+            out[2 * (i + j * ldo)] = rr;
+            out[2 * (i + j * ldo) + 1] = ri;
+        }
+    }
+}
+
 double oracle_gemm_batch(int64_t count, const int32_t* trans,
                          const int32_t* m, const int32_t* n, const int32_t* k,
                          const int32_t* lda, const int32_t* ldb, const int32_t* ldc,

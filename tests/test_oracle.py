@@ -309,3 +309,105 @@ def test_cgemm_against_numpy(lay):
                        C0.ravel(order="F"), m)
     ref = al * (Aop.astype(np.complex128) @ Bop.astype(np.complex128)) + be * C0.astype(np.complex128)
     assert np.max(np.abs(got - ref)) <= 1e-12
+
+
+# ---- ZGEMM (complex, FP64 storage): pinned independently
+
+def _zrand(rng, shape):
+    return rng.uniform(-1, 1, shape) + 1j * rng.uniform(-1, 1, shape)
+
+
+def _gauss_int(rng, shape, lo=-3, hi=4):
+    return (rng.integers(lo, hi, shape) + 1j * rng.integers(lo, hi, shape)).astype(np.complex128)
+
+
+def test_zgemm_identity_and_scalars():
+    # A = I: C* = alpha*B + beta*C0; dyadic entries keep every step exact
+    rng = np.random.Generator(np.random.PCG64(931))
+    m, n = 6, 4
+    B = _gauss_int(rng, (m, n)) / 2
+    C0 = _gauss_int(rng, (m, n)) / 4
+    al, be = 1.5 - 0.5j, 0.25 + 2j
+    got = oracle.zgemm(0, 0, m, n, m, al, np.eye(m, dtype=np.complex128).ravel(order="F"), m,
+                       B.ravel(order="F"), m, be, C0.ravel(order="F"), m)
+    assert np.array_equal(got, al * B + be * C0)
+
+
+def test_zgemm_rank_one_gaussian_integers():
+    # (x 1^T)(1 y^T) = K x y^T, exact on Gaussian integers
+    rng = np.random.Generator(np.random.PCG64(932))
+    m, n, K = 5, 3, 7
+    x, y = _gauss_int(rng, m), _gauss_int(rng, n)
+    A = np.outer(x, np.ones(K))
+    B = np.outer(np.ones(K), y)
+    got = oracle.zgemm(0, 0, m, n, K, 1j, A.ravel(order="F"), m, B.ravel(order="F"), K, 0, None, m)
+    assert np.array_equal(got, 1j * K * np.outer(x, y))
+
+
+def test_zgemm_quick_return_rules():
+    m, n, k = 2, 3, 4
+    A = np.full(m * k, np.nan, dtype=np.complex128)
+    C0 = np.arange(m * n) + 1j
+    got = oracle.zgemm(0, 0, m, n, k, 0, A, m, A, k, 2 - 1j, C0, m)
+    assert np.array_equal(got, (2 - 1j) * C0.reshape(n, m).T)
+    ones = np.ones(m * k, dtype=np.complex128)
+    got = oracle.zgemm(0, 0, m, n, k, 1, ones, m, np.ones(k * n, dtype=np.complex128), k, 0,
+                       np.full(m * n, np.nan, dtype=np.complex128), m)
+    assert np.array_equal(got, np.full((m, n), float(k), dtype=np.complex128))
+
+
+def test_zgemm_brute_force_tiny():
+    # every entry from the definition, Python complex arithmetic, parts in {-1, 0, 1}
+    rng = np.random.Generator(np.random.PCG64(933))
+    for (m, n, k) in [(1, 1, 1), (2, 3, 2), (3, 2, 4)]:
+        a = _gauss_int(rng, m * k, -1, 2)
+        b = _gauss_int(rng, k * n, -1, 2)
+        got = oracle.zgemm(0, 0, m, n, k, 1, a, m, b, k, 0, None, m)
+        for i in range(m):
+            for j in range(n):
+                assert got[i, j] == sum(complex(a[i + p * m]) * complex(b[p + j * k])
+                                        for p in range(k))
+
+
+def test_zgemm_equals_cgemm_on_widened_inputs():
+    # FP32 complex inputs widen exactly, and both loops use Eq. 2's expansion
+    # in FP64 in the same order, so the two oracles agree bit for bit
+    rng = np.random.Generator(np.random.PCG64(934))
+    m, n, k = 7, 5, 9
+    A = _crand(rng, (k, m)).ravel(order="F")
+    B = _crand(rng, (n, k)).ravel(order="F")
+    C0 = _crand(rng, (m, n)).ravel(order="F")
+    al, be = np.complex64(0.75 - 0.5j), np.complex64(-0.5 + 1j)
+    want = oracle.cgemm(1, 1, m, n, k, al, A, k, B, n, be, C0, m)
+    got = oracle.zgemm(1, 1, m, n, k, complex(al), A.astype(np.complex128), k,
+                       B.astype(np.complex128), n, complex(be), C0.astype(np.complex128), m)
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("lay", ["NN", "NT", "TN", "TT"])
+def test_zgemm_against_numpy(lay):
+    rng = np.random.Generator(np.random.PCG64(935))
+    m, n, k = 9, 7, 11
+    Aop, Bop, C0 = _zrand(rng, (m, k)), _zrand(rng, (k, n)), _zrand(rng, (m, n))
+    ta, tb = lay[0] == "T", lay[1] == "T"
+    A = (Aop.T if ta else Aop).ravel(order="F")
+    B = (Bop.T if tb else Bop).ravel(order="F")
+    al, be = 0.5 + 0.25j, -1 + 0.5j
+    got = oracle.zgemm(int(ta), int(tb), m, n, k, al, A, k if ta else m, B, n if tb else k, be,
+                       C0.ravel(order="F"), m)
+    ref = al * (Aop @ Bop) + be * C0
+    assert np.max(np.abs(got - ref)) <= 1e-13
+
+
+def test_zgemm_padded_leading_dimensions():
+    # ld > rows: the padding is never read (NaN there must not leak)
+    rng = np.random.Generator(np.random.PCG64(936))
+    m, n, k, pad = 4, 3, 5, 3
+    Aop, Bop = _gauss_int(rng, (m, k)), _gauss_int(rng, (k, n))
+    A = np.full((m + pad, k), np.nan + 0j)
+    A[:m] = Aop
+    B = np.full((k + pad, n), np.nan + 0j)
+    B[:k] = Bop
+    got = oracle.zgemm(0, 0, m, n, k, 1, A.ravel(order="F"), m + pad, B.ravel(order="F"), k + pad,
+                       0, None, m)
+    assert np.array_equal(got, Aop @ Bop)
