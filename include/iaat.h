@@ -131,10 +131,13 @@ int iaat_gemm_strided_batched(iaat_ctx_t ctx, int ta, int tb, int64_t m, int64_t
                               int64_t ldc, int64_t stride_c, int64_t batch, iaat_stream_t stream);
 
 /* DGEMM (Table 1, row D): the same operation in FP64 (operands, scalars,
- * C and accumulation), on the FP64 matrix cores.  C's 16 x 16 tiles are
- * grouped into blocks of at most 3 x 3 tiles (one wavefront each), operands
- * read in place.  Argument numbers, quick returns and NULL rules as
- * iaat_gemm / iaat_gemm_strided_batched.  Does not allocate. */
+ * C and accumulation).  Input-aware like the FP32 path: the run-time
+ * tiler's plan for (layout, M, N) from the same tile table, each plan block
+ * (one wavefront) run by the family member for that block shape instantiated
+ * for FP64 -- matrix-core grids on v_mfma_f64_16x16x4_f64, strips and
+ * K-split blocks as FMA chains -- with operands read in place.  Argument
+ * numbers, quick returns and NULL rules as iaat_gemm /
+ * iaat_gemm_strided_batched.  Does not allocate. */
 int iaat_dgemm(iaat_ctx_t ctx, int ta, int tb, int64_t m, int64_t n, int64_t k, double alpha,
                const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
                int64_t ldc, iaat_stream_t stream);
@@ -147,8 +150,8 @@ int iaat_dgemm_strided_batched(iaat_ctx_t ctx, int ta, int tb, int64_t m, int64_
 /* CGEMM (Table 1, row C): complex single precision.  A, B, C hold
  * interleaved (re, im) FP32 pairs; lda, ldb, ldc and strides count complex
  * elements; alpha and beta point to host (re, im) pairs; op(X) = X or X^T
- * (no conjugation).  Same blocking as DGEMM; each complex product is four
- * real matrix-core accumulations.  Argument numbers, quick returns (alpha =
+ * (no conjugation).  Same plan-driven execution as DGEMM; each complex
+ * product is four real FP32 products (Eq. 2) on the matrix cores.  Argument numbers, quick returns (alpha =
  * 0 + 0i or K = 0: C = beta*C; beta = 0 + 0i: C not read) and NULL rules as
  * iaat_gemm / iaat_gemm_strided_batched (-7 / -14: alpha / beta NULL). */
 int iaat_cgemm(iaat_ctx_t ctx, int ta, int tb, int64_t m, int64_t n, int64_t k, const float* alpha,
@@ -159,6 +162,61 @@ int iaat_cgemm_strided_batched(iaat_ctx_t ctx, int ta, int tb, int64_t m, int64_
                                const void* B, int64_t ldb, int64_t stride_b, const float* beta,
                                void* C, int64_t ldc, int64_t stride_c, int64_t batch,
                                iaat_stream_t stream);
+
+/* ZGEMM (Table 1, row Z): complex double precision.  A, B, C hold
+ * interleaved (re, im) FP64 pairs; lda, ldb, ldc and strides count complex
+ * elements; alpha and beta point to host (re, im) FP64 pairs; op(X) = X or
+ * X^T (no conjugation).  Each complex product is Eq. 2's four real products
+ * on the FP64 matrix cores.  Argument numbers, quick returns and NULL
+ * rules as iaat_cgemm / iaat_cgemm_strided_batched.  Does not allocate. */
+int iaat_zgemm(iaat_ctx_t ctx, int ta, int tb, int64_t m, int64_t n, int64_t k, const double* alpha,
+               const void* A, int64_t lda, const void* B, int64_t ldb, const double* beta, void* C,
+               int64_t ldc, iaat_stream_t stream);
+int iaat_zgemm_strided_batched(iaat_ctx_t ctx, int ta, int tb, int64_t m, int64_t n, int64_t k,
+                               const double* alpha, const void* A, int64_t lda, int64_t stride_a,
+                               const void* B, int64_t ldb, int64_t stride_b, const double* beta,
+                               void* C, int64_t ldc, int64_t stride_c, int64_t batch,
+                               iaat_stream_t stream);
+
+/* Element types of the DGEMM / CGEMM / ZGEMM forms (Table 1, rows D, C, Z). */
+enum {
+    IAAT_DT_F64 = 1,  /* real FP64 */
+    IAAT_DT_C64 = 2,  /* complex FP32: interleaved (re, im) float pairs */
+    IAAT_DT_C128 = 3  /* complex FP64: interleaved (re, im) double pairs */
+};
+
+/* One problem of an uneven D/C/Z batch: 96 bytes, naturally aligned.
+ * Leading dimensions count elements (complex elements for C64 / C128).
+ * alpha and beta are (re, im); the imaginary parts are ignored for
+ * IAAT_DT_F64, and for IAAT_DT_C64 both parts are rounded to FP32. */
+typedef struct iaat_xproblem {
+    const void* A;   /* device pointer */
+    const void* B;   /* device pointer */
+    void* C;         /* device pointer */
+    int32_t trans;   /* bit 0: op(A) = A^T; bit 1: op(B) = B^T; other bits 0 */
+    int32_t m, n, k;
+    int32_t lda, ldb, ldc;
+    int32_t reserved0;
+    double alpha[2];
+    double beta[2];
+    int64_t reserved1;
+} iaat_xproblem;
+
+/* iaat_xgemm_vbatched runs `count` independent problems of element type
+ * `dtype` (IAAT_DT_*) whose descriptors are in device memory
+ * (Section V-B's input-aware execution applied per problem: each problem's
+ * plan comes from the run-time tiler's table for its layout and M x N, the
+ * same table the FP32 path uses, and every plan block runs on the family
+ * member for that block shape and element type).  One wavefront per
+ * problem.  status: NULL, or a device int32 array of `count` entries that
+ * receives each problem's validation code (0, or the negative argument
+ * number iaat_gemm would return: -3 trans, -4 m, ... -14 ldc) -- a problem
+ * that fails validation is skipped.  Quick returns per problem as
+ * iaat_cgemm.  Returns 0, -1 ctx NULL, -2 probs NULL with count > 0, -3
+ * count < 0 or above 2^40, -4 dtype.  Does not allocate; the descriptors
+ * and C regions must not overlap between problems. */
+int iaat_xgemm_vbatched(iaat_ctx_t ctx, int dtype, const iaat_xproblem* probs_dev, int64_t count,
+                        int32_t* status_dev, iaat_stream_t stream);
 
 /* ------------------------------------------------- many uneven problems */
 

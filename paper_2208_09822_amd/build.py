@@ -17,7 +17,7 @@ OBJ_DIR = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libiaat.so")
 ROOT = os.path.dirname(PKG)
 
-SOURCES = ["kernels.hip", "batched.hip", "precision.hip", "traditional.hip", "dgemm.hip", "cgemm.hip", "api.cpp", "serve.cpp", "tiler.cpp"]
+SOURCES = ["kernels.hip", "batched.hip", "precision.hip", "traditional.hip", "xgemm.hip", "api.cpp", "serve.cpp", "tiler.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",

@@ -258,53 +258,69 @@ int iaat_gemm_strided_batched(iaat_ctx_t ctx, int ta, int tb, int64_t m, int64_t
   return e == hipSuccess ? IAAT_OK : hip_fail(e, "iaat_gemm_strided_batched: launch");
 }
 
+// DGEMM / CGEMM / ZGEMM, one problem or a same-size strided batch: the
+// FP32 path's argument checks, then the plan-driven family kernels.
+static int x_strided(iaat_ctx_t ctx, int dt, const char* name, int ta, int tb, int64_t m, int64_t n,
+                     int64_t k, double alpha_re, double alpha_im, const void* A, int64_t lda,
+                     int64_t stride_a, const void* B, int64_t ldb, int64_t stride_b, double beta_re,
+                     double beta_im, void* C, int64_t ldc, int64_t stride_c, int64_t batch,
+                     iaat_stream_t stream) {
+  if (!ctx) return fail(-1, "%s: ctx is NULL", name);
+  if (ta != IAAT_OP_N && ta != IAAT_OP_T) return fail(-2, "%s: ta=%d", name, ta);
+  if (tb != IAAT_OP_N && tb != IAAT_OP_T) return fail(-3, "%s: tb=%d", name, tb);
+  const int layout = ta | (tb << 1);
+  const bool a0 = alpha_re == 0.0 && alpha_im == 0.0;
+  // validate reads alpha only as "is it zero"
+  int st = validate(layout, m, n, k, lda, ldb, ldc, a0 ? 0.0f : 1.0f, A, B, C);
+  static const int remap[15] = {0, 0, -2, -3, -4, -5, -6, 0, -8, -9, -11, -12, 0, -15, -16};
+  if (st != 0) {
+    st = remap[-st];
+    return fail(st, "%s: invalid argument %d", name, -st);
+  }
+  if (batch < 0) return fail(-18, "%s: batch=%lld", name, (long long)batch);
+  if (stride_a < 0) return fail(-10, "%s: stride_a=%lld", name, (long long)stride_a);
+  if (stride_b < 0) return fail(-13, "%s: stride_b=%lld", name, (long long)stride_b);
+  if (batch > 1 && m > 0 && n > 0 && stride_c < ldc * n)
+    return fail(-17, "%s: stride_c=%lld < ldc*n (outputs overlap)", name, (long long)stride_c);
+  if (m == 0 || n == 0 || batch == 0) return IAAT_OK;
+  DeviceGuard g(ctx->device);
+  hipStream_t s = (hipStream_t)stream;
+  XProb P{A, B, C, (int)m, (int)n, (int)k, (int)lda, (int)ldb, (int)ldc,
+          alpha_re, alpha_im, beta_re, beta_im};
+  hipError_t e;
+  if (a0 || k == 0) {
+    e = launch_xscale(dt, P, stride_c, batch, s);
+  } else {
+    const int64_t nsm = (m + kSuper - 1) / kSuper, nsn = (n + kSuper - 1) / kSuper;
+    if (nsm * nsn > 0x7fffffffLL)
+      return fail(IAAT_ERR_UNSUPPORTED, "%s: %lld x %lld is too large", name, (long long)m,
+                  (long long)n);
+    e = launch_xgemm(dt, P, layout, stride_a, stride_b, stride_c, batch, ctx->table_dev, (int)nsm,
+                     (int)nsn, max_plan_blocks(ctx, layout, m, n, nsm, nsn), s);
+  }
+  return e == hipSuccess ? IAAT_OK : hip_fail(e, name);
+}
+
+// Argument numbers of the one-problem signatures, from the strided ones.
+static int one_problem_rc(int rc) {
+  static const int back[19] = {0, -1, -2, -3, -4, -5, -6, -7, -8, -9, 0, -10, -11, 0, -12, -13, -14, 0, 0};
+  return (rc < 0 && rc > -19) ? back[-rc] : rc;
+}
+
 int iaat_dgemm_strided_batched(iaat_ctx_t ctx, int ta, int tb, int64_t m, int64_t n, int64_t k,
                                double alpha, const double* A, int64_t lda, int64_t stride_a,
                                const double* B, int64_t ldb, int64_t stride_b, double beta,
                                double* C, int64_t ldc, int64_t stride_c, int64_t batch,
                                iaat_stream_t stream) {
-  if (!ctx) return fail(-1, "iaat_dgemm: ctx is NULL");
-  if (ta != IAAT_OP_N && ta != IAAT_OP_T) return fail(-2, "iaat_dgemm: ta=%d", ta);
-  if (tb != IAAT_OP_N && tb != IAAT_OP_T) return fail(-3, "iaat_dgemm: tb=%d", tb);
-  const int layout = ta | (tb << 1);
-  // validate reads alpha only as "is it zero"
-  int st = validate(layout, m, n, k, lda, ldb, ldc, alpha != 0.0 ? 1.0f : 0.0f, A, B, C);
-  static const int remap[15] = {0, 0, -2, -3, -4, -5, -6, 0, -8, -9, -11, -12, 0, -15, -16};
-  if (st != 0) {
-    st = remap[-st];
-    return fail(st, "iaat_dgemm: invalid argument %d", -st);
-  }
-  if (batch < 0) return fail(-18, "iaat_dgemm: batch=%lld", (long long)batch);
-  if (stride_a < 0) return fail(-10, "iaat_dgemm: stride_a=%lld", (long long)stride_a);
-  if (stride_b < 0) return fail(-13, "iaat_dgemm: stride_b=%lld", (long long)stride_b);
-  if (batch > 1 && m > 0 && n > 0 && stride_c < ldc * n)
-    return fail(-17, "iaat_dgemm: stride_c=%lld < ldc*n (outputs overlap)", (long long)stride_c);
-  if (m == 0 || n == 0 || batch == 0) return IAAT_OK;
-  if (m > 0x7fff0000LL || n > 0x7fff0000LL)
-    return fail(IAAT_ERR_UNSUPPORTED, "iaat_dgemm: %lld x %lld is too large", (long long)m, (long long)n);
-  DeviceGuard g(ctx->device);
-  hipStream_t s = (hipStream_t)stream;
-  hipError_t e;
-  if (alpha == 0.0 || k == 0) {
-    e = launch_dscale(C, (int)m, (int)n, ldc, beta, stride_c, batch, s);
-  } else {
-    const int64_t tm = (m + 15) / 16, tn = (n + 15) / 16;
-    if (((tm + 2) / 3) * ((tn + 2) / 3) > 0x7fffffffLL)
-      return fail(IAAT_ERR_UNSUPPORTED, "iaat_dgemm: too many blocks");
-    DProb P{A, B, C, (int)m, (int)n, (int)k, (int)lda, (int)ldb, (int)ldc, alpha, beta};
-    e = launch_dgemm(P, layout, stride_a, stride_b, stride_c, batch, s);
-  }
-  return e == hipSuccess ? IAAT_OK : hip_fail(e, "iaat_dgemm: launch");
+  return x_strided(ctx, IAAT_DT_F64, "iaat_dgemm", ta, tb, m, n, k, alpha, 0.0, A, lda, stride_a, B,
+                   ldb, stride_b, beta, 0.0, C, ldc, stride_c, batch, stream);
 }
 
 int iaat_dgemm(iaat_ctx_t ctx, int ta, int tb, int64_t m, int64_t n, int64_t k, double alpha,
                const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
                int64_t ldc, iaat_stream_t stream) {
-  const int rc = iaat_dgemm_strided_batched(ctx, ta, tb, m, n, k, alpha, A, lda, 0, B, ldb, 0, beta,
-                                            C, ldc, 0, 1, stream);
-  // report argument numbers of the one-problem signature
-  static const int back[19] = {0, -1, -2, -3, -4, -5, -6, -7, -8, -9, 0, -10, -11, 0, -12, -13, -14, 0, 0};
-  return (rc < 0 && rc > -19) ? back[-rc] : rc;
+  return one_problem_rc(iaat_dgemm_strided_batched(ctx, ta, tb, m, n, k, alpha, A, lda, 0, B, ldb, 0,
+                                                   beta, C, ldc, 0, 1, stream));
 }
 
 int iaat_cgemm_strided_batched(iaat_ctx_t ctx, int ta, int tb, int64_t m, int64_t n, int64_t k,
@@ -313,46 +329,51 @@ int iaat_cgemm_strided_batched(iaat_ctx_t ctx, int ta, int tb, int64_t m, int64_
                                void* C, int64_t ldc, int64_t stride_c, int64_t batch,
                                iaat_stream_t stream) {
   if (!ctx) return fail(-1, "iaat_cgemm: ctx is NULL");
-  if (ta != IAAT_OP_N && ta != IAAT_OP_T) return fail(-2, "iaat_cgemm: ta=%d", ta);
-  if (tb != IAAT_OP_N && tb != IAAT_OP_T) return fail(-3, "iaat_cgemm: tb=%d", tb);
   if (!alpha) return fail(-7, "iaat_cgemm: alpha is NULL");
   if (!beta) return fail(-14, "iaat_cgemm: beta is NULL");
-  const int layout = ta | (tb << 1);
-  const bool a0 = alpha[0] == 0.0f && alpha[1] == 0.0f;
-  int st = validate(layout, m, n, k, lda, ldb, ldc, a0 ? 0.0f : 1.0f, A, B, C);
-  static const int remap[15] = {0, 0, -2, -3, -4, -5, -6, 0, -8, -9, -11, -12, 0, -15, -16};
-  if (st != 0) {
-    st = remap[-st];
-    return fail(st, "iaat_cgemm: invalid argument %d", -st);
-  }
-  if (batch < 0) return fail(-18, "iaat_cgemm: batch=%lld", (long long)batch);
-  if (stride_a < 0) return fail(-10, "iaat_cgemm: stride_a=%lld", (long long)stride_a);
-  if (stride_b < 0) return fail(-13, "iaat_cgemm: stride_b=%lld", (long long)stride_b);
-  if (batch > 1 && m > 0 && n > 0 && stride_c < ldc * n)
-    return fail(-17, "iaat_cgemm: stride_c=%lld < ldc*n (outputs overlap)", (long long)stride_c);
-  if (m == 0 || n == 0 || batch == 0) return IAAT_OK;
-  if (m > 0x7fff0000LL || n > 0x7fff0000LL)
-    return fail(IAAT_ERR_UNSUPPORTED, "iaat_cgemm: %lld x %lld is too large", (long long)m, (long long)n);
-  DeviceGuard g(ctx->device);
-  hipStream_t s = (hipStream_t)stream;
-  hipError_t e;
-  if (a0 || k == 0) {
-    e = launch_cscale((float*)C, (int)m, (int)n, ldc, beta[0], beta[1], stride_c, batch, s);
-  } else {
-    CProb P{(const float*)A, (const float*)B, (float*)C, (int)m, (int)n, (int)k, (int)lda, (int)ldb,
-            (int)ldc, alpha[0], alpha[1], beta[0], beta[1]};
-    e = launch_cgemm(P, layout, stride_a, stride_b, stride_c, batch, s);
-  }
-  return e == hipSuccess ? IAAT_OK : hip_fail(e, "iaat_cgemm: launch");
+  return x_strided(ctx, IAAT_DT_C64, "iaat_cgemm", ta, tb, m, n, k, alpha[0], alpha[1], A, lda,
+                   stride_a, B, ldb, stride_b, beta[0], beta[1], C, ldc, stride_c, batch, stream);
 }
 
 int iaat_cgemm(iaat_ctx_t ctx, int ta, int tb, int64_t m, int64_t n, int64_t k, const float* alpha,
                const void* A, int64_t lda, const void* B, int64_t ldb, const float* beta, void* C,
                int64_t ldc, iaat_stream_t stream) {
-  const int rc = iaat_cgemm_strided_batched(ctx, ta, tb, m, n, k, alpha, A, lda, 0, B, ldb, 0, beta,
-                                            C, ldc, 0, 1, stream);
-  static const int back[19] = {0, -1, -2, -3, -4, -5, -6, -7, -8, -9, 0, -10, -11, 0, -12, -13, -14, 0, 0};
-  return (rc < 0 && rc > -19) ? back[-rc] : rc;
+  return one_problem_rc(iaat_cgemm_strided_batched(ctx, ta, tb, m, n, k, alpha, A, lda, 0, B, ldb, 0,
+                                                   beta, C, ldc, 0, 1, stream));
+}
+
+int iaat_zgemm_strided_batched(iaat_ctx_t ctx, int ta, int tb, int64_t m, int64_t n, int64_t k,
+                               const double* alpha, const void* A, int64_t lda, int64_t stride_a,
+                               const void* B, int64_t ldb, int64_t stride_b, const double* beta,
+                               void* C, int64_t ldc, int64_t stride_c, int64_t batch,
+                               iaat_stream_t stream) {
+  if (!ctx) return fail(-1, "iaat_zgemm: ctx is NULL");
+  if (!alpha) return fail(-7, "iaat_zgemm: alpha is NULL");
+  if (!beta) return fail(-14, "iaat_zgemm: beta is NULL");
+  return x_strided(ctx, IAAT_DT_C128, "iaat_zgemm", ta, tb, m, n, k, alpha[0], alpha[1], A, lda,
+                   stride_a, B, ldb, stride_b, beta[0], beta[1], C, ldc, stride_c, batch, stream);
+}
+
+int iaat_zgemm(iaat_ctx_t ctx, int ta, int tb, int64_t m, int64_t n, int64_t k, const double* alpha,
+               const void* A, int64_t lda, const void* B, int64_t ldb, const double* beta, void* C,
+               int64_t ldc, iaat_stream_t stream) {
+  return one_problem_rc(iaat_zgemm_strided_batched(ctx, ta, tb, m, n, k, alpha, A, lda, 0, B, ldb, 0,
+                                                   beta, C, ldc, 0, 1, stream));
+}
+
+int iaat_xgemm_vbatched(iaat_ctx_t ctx, int dtype, const iaat_xproblem* probs_dev, int64_t count,
+                        int32_t* status_dev, iaat_stream_t stream) {
+  if (!ctx) return fail(-1, "iaat_xgemm_vbatched: ctx is NULL");
+  if (count < 0 || count > (1LL << 40))
+    return fail(-3, "iaat_xgemm_vbatched: count=%lld", (long long)count);
+  if (count > 0 && !probs_dev) return fail(-2, "iaat_xgemm_vbatched: probs is NULL");
+  if (dtype != IAAT_DT_F64 && dtype != IAAT_DT_C64 && dtype != IAAT_DT_C128)
+    return fail(-4, "iaat_xgemm_vbatched: dtype=%d", dtype);
+  if (count == 0) return IAAT_OK;
+  DeviceGuard g(ctx->device);
+  const hipError_t e = launch_xgemm_vbatched(dtype, probs_dev, count, status_dev, ctx->table_dev,
+                                             (hipStream_t)stream);
+  return e == hipSuccess ? IAAT_OK : hip_fail(e, "iaat_xgemm_vbatched: launch");
 }
 
 struct iaat_tradplan {

@@ -64,31 +64,23 @@ struct CopySpan {
 };
 hipError_t launch_copy_spans(const CopySpan* spans, int64_t count, int grid, hipStream_t stream);
 
-// DGEMM (dgemm.hip): one problem (or a same-size strided batch).
-struct DProb {
-  const double* A;
-  const double* B;
-  double* C;
+// DGEMM / CGEMM / ZGEMM (xgemm.hip): one problem or super-block as the
+// family members see it; pointers to the stored matrices, dimensions in
+// elements (complex elements for complex types), scalars in FP64 (rounded
+// to FP32 for complex FP32).
+struct XProb {
+  const void* A;
+  const void* B;
+  void* C;
   int m, n, k, lda, ldb, ldc;
-  double alpha, beta;
+  double alpha_re, alpha_im, beta_re, beta_im;
 };
-hipError_t launch_dgemm(const DProb& P, int layout, int64_t sa, int64_t sb, int64_t sc, int64_t batch,
-                        hipStream_t stream);
-hipError_t launch_dscale(double* C, int m, int n, int64_t ldc, double beta, int64_t sc, int64_t batch,
-                         hipStream_t stream);
-
-// CGEMM (cgemm.hip): interleaved complex FP32, complex scalars.
-struct CProb {
-  const float* A;  // (re, im) pairs
-  const float* B;
-  float* C;
-  int m, n, k, lda, ldb, ldc;  // in complex elements
-  float alpha_re, alpha_im, beta_re, beta_im;
-};
-hipError_t launch_cgemm(const CProb& P, int layout, int64_t sa, int64_t sb, int64_t sc, int64_t batch,
-                        hipStream_t stream);
-hipError_t launch_cscale(float* C, int m, int n, int64_t ldc, float beta_re, float beta_im, int64_t sc,
-                         int64_t batch, hipStream_t stream);
+hipError_t launch_xgemm(int dt, const XProb& P, int layout, int64_t sa, int64_t sb, int64_t sc,
+                        int64_t batch, const PlanEntry* table_dev, int nsm, int nsn, int max_blocks,
+                        hipStream_t s);
+hipError_t launch_xscale(int dt, const XProb& P, int64_t sc, int64_t batch, hipStream_t s);
+hipError_t launch_xgemm_vbatched(int dt, const iaat_xproblem* probs, int64_t count, int32_t* status,
+                                 const PlanEntry* table_dev, hipStream_t s);
 
 // Traditional pack + uniform-tile scheme (traditional.hip), for ablation.
 struct TradProb {

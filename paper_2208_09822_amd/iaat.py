@@ -123,6 +123,11 @@ def lib():
                 "iaat_dgemm_strided_batched": (i32, [vp, i32, i32, i64, i64, i64, ctypes.c_double,
                                                      vp, i64, i64, vp, i64, i64, ctypes.c_double,
                                                      vp, i64, i64, i64, vp]),
+                "iaat_zgemm": (i32, [vp, i32, i32, i64, i64, i64, vp, vp, i64, vp, i64, vp, vp, i64,
+                                     vp]),
+                "iaat_zgemm_strided_batched": (i32, [vp, i32, i32, i64, i64, i64, vp, vp, i64, i64,
+                                                     vp, i64, i64, vp, vp, i64, i64, i64, vp]),
+                "iaat_xgemm_vbatched": (i32, [vp, i32, vp, i64, vp, vp]),
                 "iaat_trad_pack": (i32, [vp, vp]),
                 "iaat_trad_compute": (i32, [vp, vp]),
                 "iaat_trad_workspace_bytes": (i64, [vp]),
@@ -237,6 +242,39 @@ def iaat_cgemm_strided_batched(ctx, ta, tb, m, n, k, alpha, A, lda, stride_a, B,
     _check(lib().iaat_cgemm_strided_batched(ctx, ta, tb, m, n, k, _cscalar(alpha), A or None, lda,
                                             stride_a, B or None, ldb, stride_b, _cscalar(beta),
                                             C or None, ldc, stride_c, batch, stream or None))
+
+
+def _zscalar(x):
+    x = complex(x)
+    return (ctypes.c_double * 2)(x.real, x.imag)
+
+
+def iaat_zgemm(ctx, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, stream=0) -> None:
+    _check(lib().iaat_zgemm(ctx, ta, tb, m, n, k, _zscalar(alpha), A or None, lda, B or None, ldb,
+                            _zscalar(beta), C or None, ldc, stream or None))
+
+
+def iaat_zgemm_strided_batched(ctx, ta, tb, m, n, k, alpha, A, lda, stride_a, B, ldb, stride_b,
+                               beta, C, ldc, stride_c, batch, stream=0) -> None:
+    _check(lib().iaat_zgemm_strided_batched(ctx, ta, tb, m, n, k, _zscalar(alpha), A or None, lda,
+                                            stride_a, B or None, ldb, stride_b, _zscalar(beta),
+                                            C or None, ldc, stride_c, batch, stream or None))
+
+
+IAAT_DT_F64, IAAT_DT_C64, IAAT_DT_C128 = 1, 2, 3
+
+# iaat_xproblem (96 bytes)
+XPROBLEM_DTYPE = np.dtype([("A", np.uint64), ("B", np.uint64), ("C", np.uint64),
+                           ("trans", np.int32), ("m", np.int32), ("n", np.int32), ("k", np.int32),
+                           ("lda", np.int32), ("ldb", np.int32), ("ldc", np.int32),
+                           ("reserved0", np.int32), ("alpha", np.float64, (2,)),
+                           ("beta", np.float64, (2,)), ("reserved1", np.int64)])
+assert XPROBLEM_DTYPE.itemsize == 96
+
+
+def iaat_xgemm_vbatched(ctx, dtype, probs_dev, count, status_dev=0, stream=0) -> None:
+    _check(lib().iaat_xgemm_vbatched(ctx, dtype, probs_dev or None, count, status_dev or None,
+                                     stream or None))
 
 
 def iaat_trad_create(ctx, probs_host: np.ndarray) -> int:
