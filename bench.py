@@ -158,59 +158,82 @@ def traditional_leg(iaat, h, ps, desc, iaat_ms, dev, stream):
             "algorithmic_bytes": {"iaat": int(ab + c), "traditional": int(2 * ab + 2 * ws + c)}}
 
 
-def dgemm_leg(iaat, h, dev, stream):
-    """DGEMM same-size batches (FP64 operands on the FP64 matrix cores)."""
-    import torch
-    res = {}
-    sp = stream.cuda_stream
-    for (m, n, k, batch) in ((16, 16, 16, 65536), (80, 80, 80, 4096)):
-        g = torch.Generator(device="cpu").manual_seed(m + 1)
-        A = (torch.rand(batch * m * k, generator=g, dtype=torch.float64) * 2 - 1).to(dev)
-        B = (torch.rand(batch * k * n, generator=g, dtype=torch.float64) * 2 - 1).to(dev)
-        C = (torch.rand(batch * m * n, generator=g, dtype=torch.float64) * 2 - 1).to(dev)
-        ms = _events_ms(torch, stream, lambda: iaat.iaat_dgemm_strided_batched(
-            h, 0, 0, m, n, k, 1.0, A.data_ptr(), m, m * k, B.data_ptr(), k, k * n, 1.0,
-            C.data_ptr(), m, m * n, batch, sp), 10)
-        byt = 8.0 * batch * (m * k + k * n + 2 * m * n)
-        res["nn%d_x%d" % (m, batch)] = {"us": round(ms * 1e3, 1), "gbs": round(byt / ms / 1e6, 1),
-                                        "hbm_frac": round(byt / ms / 1e6 / HBM_PEAK_GBS, 4),
-                                        "gflops": round(2.0 * batch * m * n * k / ms / 1e6, 1)}
-    return res
+XGEMM_TYPES = {  # name: (IAAT_DT_*, bytes per element, real flops per multiply-add)
+    "dgemm": (1, 8, 2.0), "cgemm": (2, 8, 8.0), "zgemm": (3, 16, 8.0)}
 
 
-def cgemm_leg(iaat, h, dev, stream):
-    """CGEMM same-size batches (interleaved complex FP32); flops 8MNK (Eq. 2)."""
+def xgemm_leg(iaat, inputs, h, dev, stream, name):
+    """DGEMM / CGEMM / ZGEMM (Table 1 rows D, C, Z) on the plan-driven path:
+    same-size strided batches, and an uneven batch of 16,384 problems (M, N,
+    K uniform in 1..80, layouts uniform) through iaat_xgemm_vbatched.  Flops
+    count 2MNK real or 8MNK complex (Eq. 2); bytes count A, B and C read
+    plus C written once each."""
+    import numpy as np
     import torch
+    dt, eb, fpm = XGEMM_TYPES[name]
+    real = torch.float64 if eb == 16 or name == "dgemm" else torch.float32
+    per = 2 if name != "dgemm" else 1  # reals per element
     res = {}
     sp = stream.cuda_stream
+    fns = {"dgemm": iaat.iaat_dgemm_strided_batched, "cgemm": iaat.iaat_cgemm_strided_batched,
+           "zgemm": iaat.iaat_zgemm_strided_batched}
     for (m, n, k, batch) in ((16, 16, 16, 65536), (80, 80, 80, 4096)):
-        g = torch.Generator(device="cpu").manual_seed(m + 2)
-        mk = lambda c: (torch.rand(2 * c, generator=g) * 2 - 1).to(dev)
+        g = torch.Generator(device="cpu").manual_seed(m + dt)
+        mk = lambda c: (torch.rand(per * c, generator=g, dtype=real) * 2 - 1).to(dev)
         A, B, C = mk(batch * m * k), mk(batch * k * n), mk(batch * m * n)
-        ms = _events_ms(torch, stream, lambda: iaat.iaat_cgemm_strided_batched(
+        ms = _events_ms(torch, stream, lambda: fns[name](
             h, 0, 0, m, n, k, 1.0, A.data_ptr(), m, m * k, B.data_ptr(), k, k * n, 1.0,
             C.data_ptr(), m, m * n, batch, sp), 10)
-        byt = 8.0 * batch * (m * k + k * n + 2 * m * n)
+        byt = float(eb) * batch * (m * k + k * n + 2 * m * n)
         res["nn%d_x%d" % (m, batch)] = {"us": round(ms * 1e3, 1), "gbs": round(byt / ms / 1e6, 1),
                                         "hbm_frac": round(byt / ms / 1e6 / HBM_PEAK_GBS, 4),
-                                        "gflops": round(8.0 * batch * m * n * k / ms / 1e6, 1)}
+                                        "gflops": round(fpm * batch * m * n * k / ms / 1e6, 1)}
+    # uneven batch
+    count = 16384
+    rng = np.random.Generator(np.random.PCG64(inputs.SEED_BASE + 40 + dt))
+    shp = inputs.uneven_shapes(count, rng)
+    lay = np.array([inputs.LAYOUT_BITS[x[0]] for x in shp], np.int32)
+    M, N, K = (np.array([x[i] for x in shp], np.int64) for i in (1, 2, 3))
+    ta, tb = (lay & 1).astype(bool), (lay & 2).astype(bool)
+    lda = np.where(ta, K, M)
+    ldb = np.where(tb, N, K)
+    sa, sb, sc = M * K, K * N, M * N
+    tot = np.cumsum(np.stack([sa, sb, sc], 1).ravel())
+    start = np.concatenate([[0], tot[:-1]]).reshape(count, 3)
+    g = torch.Generator(device="cpu").manual_seed(77 + dt)
+    buf = (torch.rand(per * int(tot[-1]), generator=g, dtype=real) * 2 - 1).to(dev)
+    d = np.zeros(count, dtype=iaat.XPROBLEM_DTYPE)
+    base = buf.data_ptr()
+    d["A"], d["B"], d["C"] = (base + eb * start[:, i].astype(np.uint64) for i in range(3))
+    d["trans"], d["m"], d["n"], d["k"] = lay, M, N, K
+    d["lda"], d["ldb"], d["ldc"] = lda, ldb, M
+    d["alpha"][:, 0] = 1.0
+    d["beta"][:, 0] = 1.0
+    dd = torch.from_numpy(d.view(np.uint8)).to(dev)
+    ms = _events_ms(torch, stream, lambda: iaat.iaat_xgemm_vbatched(h, dt, dd.data_ptr(), count, 0, sp), 5)
+    byt = float(eb) * float(np.sum(sa + sb + 2 * sc))
+    fl = fpm * float(np.sum(M * N * K))
+    res["uneven%d" % count] = {"us": round(ms * 1e3, 1), "gbs": round(byt / ms / 1e6, 1),
+                               "hbm_frac": round(byt / ms / 1e6 / HBM_PEAK_GBS, 4),
+                               "gflops": round(fl / ms / 1e6, 1)}
+    print("[bench] %s uneven %d: %.1f us" % (name, count, ms * 1e3), file=sys.stderr, flush=True)
     return res
 
 
 def precision_leg(iaat, inputs, h, dev, stream):
-    """Reduced-precision inputs on the sweep grid (2 problems per shape,
+    """Reduced-precision inputs on the sweep grid (16 problems per shape,
     |x| = 10^U(-3,3)): on-device quantisation and the batched GEMM, per type.
     Bytes count A and B at the stored width (4 bytes for a bf16 hi/lo pair)."""
     import numpy as np
     import torch
-    ps = inputs.precision_problems(per_shape=2)
+    ps = inputs.precision_problems(per_shape=16)
     buf = torch.from_numpy(ps.buf).to(dev)
     sp = stream.cuda_stream
     fl = ps.flops()
     m, n, k = (x.astype(np.float64) for x in (ps.m, ps.n, ps.k))
     ab_elems = float(np.sum(m * k + k * n))
     c_bytes = float(np.sum(4.0 * m * n * 2))  # beta = 1: C read and written
-    res = {"workload": "sweep grid x2 (%d problems), log-uniform entries" % ps.count}
+    res = {"workload": "sweep grid x16 (%d problems), log-uniform entries" % ps.count}
     for prec in (iaat.IAAT_PREC_BF16, iaat.IAAT_PREC_F16, iaat.IAAT_PREC_F8E4M3, iaat.IAAT_PREC_BF16X3):
         eb = iaat.PREC_ELEM_BYTES[prec] * iaat.PREC_SPAN[prec]
         codes = torch.zeros(iaat.PREC_SPAN[prec] * ps.buf.shape[0] * iaat.PREC_ELEM_BYTES[prec],
@@ -266,65 +289,104 @@ def serve_leg(iaat, inputs, h, dev, seconds):
         print("[bench] serve %dk req/s: p50 %.3f ms p99 %.3f ms (p99 submit lag %.3f ms)" % (
             rate / 1000, np.percentile(lat, 50) * 1e3, np.percentile(lat, 99) * 1e3,
             st["p99_submit_lag"] * 1e3), file=sys.stderr, flush=True)
+    # the per-call baseline: the 20k req/s trace's first requests, closed loop
+    # (no arrival waits), one iaat_gemm launch per GEMM on one stream -- the
+    # most requests per second that path sustains, to set beside the offered
+    # rates above
+    t, cnt = inputs.poisson_trace(20000.0, seconds, seed=inputs.SEED_BASE + 14)
+    idx = inputs.pool_indices(int(cnt.sum()), ps.count, seed=inputs.SEED_BASE + 15)
+    nreq = min(int(t.shape[0]), 4000)
+    ng = int(cnt[:nreq].sum())
+    base = buf.data_ptr()
+    L = iaat.lib()
+    sp = torch.cuda.current_stream(dev).cuda_stream
+    qs = idx[:ng].tolist()
+    tr = ps.trans.tolist(); mm = ps.m.tolist(); nn = ps.n.tolist(); kk = ps.k.tolist()
+    la = ps.lda.tolist(); lb = ps.ldb.tolist(); lc = ps.ldc.tolist()
+    ao = (base + 4 * ps.a_off).tolist(); bo = (base + 4 * ps.b_off).tolist()
+    co = (base + 4 * ps.c_off).tolist()
+    torch.cuda.synchronize(dev)
+    w0 = time.perf_counter()
+    for q in qs:
+        tq = tr[q]
+        L.iaat_gemm(h, tq & 1, tq >> 1, mm[q], nn[q], kk[q], 1.0, ao[q], la[q], bo[q], lb[q], 1.0,
+                    co[q], lc[q], sp)
+    torch.cuda.synchronize(dev)
+    wall = time.perf_counter() - w0
+    res["per_call_baseline"] = {
+        "requests": nreq, "gemms": ng, "seconds": round(wall, 3),
+        "req_per_s": round(nreq / wall, 1), "gemms_per_s": round(ng / wall, 1),
+        "gflops": round(float(pf[idx[:ng]].sum()) / wall / 1e9, 1),
+        "note": "closed loop, one launch per GEMM; compare req_per_s with the offered rates"}
+    print("[bench] serve per-call baseline: %.0f req/s" % (nreq / wall), file=sys.stderr, flush=True)
     return res
 
 
-def sweep(iaat, inputs, dev, per_shape, out_path):
-    """The plain-method sweep: for every (layout, M, N, K) of the grid, the
-    same `per_shape` problems one iaat_gemm call each and as one batched
-    launch (ld = stored rows, U[-1,1], alpha = beta = 1)."""
+def sweep(iaat, inputs, dev, per_shape, out_path=None, percall_sample=16, chunk_shapes=1024):
+    """The plain-method sweep (every (layout, M, N, K) of the grid, ld =
+    stored rows, U[-1,1], alpha = beta = 1): each shape's `per_shape`
+    problems as one batched launch, and the first `percall_sample` of them
+    one iaat_gemm call each (timing sampled; parity over every problem is a
+    GPU test).  Problems are generated a chunk of shapes at a time, so memory
+    stays bounded at 256 per shape.  Writes the per-shape CSV when
+    `out_path` is given; returns the per-layout summary."""
     import numpy as np
     import torch
+    from paper_2208_09822_amd import autotune
     shapes = inputs.sweep_shapes()
-    ps = inputs.sweep_problems(per_shape=per_shape)
-    buf = torch.from_numpy(ps.buf).to(dev)
-    base = buf.data_ptr()
     stream = torch.cuda.current_stream(dev)
     sp = stream.cuda_stream
     ctx = iaat.Context(0)
-    from paper_2208_09822_amd import autotune
     autotune.apply(ctx.handle)
-    desc = torch.from_numpy(iaat.descriptors(ps, base).view(np.uint8)).to(dev)
     L = iaat.lib()
-    ao = (base + 4 * ps.a_off).tolist(); bo = (base + 4 * ps.b_off).tolist()
-    co = (base + 4 * ps.c_off).tolist()
     rows = []
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.time()
-    for si, (lay, m, n, k) in enumerate(shapes):
-        q0 = si * per_shape
-        t = inputs.LAYOUT_BITS[lay]
-        lda, ldb = int(ps.lda[q0]), int(ps.ldb[q0])
+    ns = min(percall_sample, per_shape)
+    for c0 in range(0, len(shapes), chunk_shapes):
+        chunk = shapes[c0:c0 + chunk_shapes]
+        ps = inputs.sweep_problems(per_shape=per_shape, shapes=chunk, seed=inputs.SEED_BASE + 1 + c0)
+        buf = torch.from_numpy(ps.buf).to(dev)
+        base = buf.data_ptr()
+        desc = torch.from_numpy(iaat.descriptors(ps, base).view(np.uint8)).to(dev)
+        ao = (base + 4 * ps.a_off).tolist(); bo = (base + 4 * ps.b_off).tolist()
+        co = (base + 4 * ps.c_off).tolist()
+        for si, (lay, m, n, k) in enumerate(chunk):
+            q0 = si * per_shape
+            t = inputs.LAYOUT_BITS[lay]
+            lda, ldb = int(ps.lda[q0]), int(ps.ldb[q0])
 
-        def calls():
-            for q in range(q0, q0 + per_shape):
-                L.iaat_gemm(ctx.handle, t & 1, t >> 1, m, n, k, 1.0, ao[q], lda, bo[q], ldb, 1.0,
-                            co[q], m, sp)
-        calls()
-        a.record(stream)
-        calls()
-        b.record(stream)
-        b.synchronize()
-        ms_pc = a.elapsed_time(b)
-        dptr = desc.data_ptr() + 64 * q0
-        iaat.iaat_gemm_vbatched_device(ctx.handle, dptr, per_shape, stream=sp)
-        a.record(stream)
-        iaat.iaat_gemm_vbatched_device(ctx.handle, dptr, per_shape, stream=sp)
-        b.record(stream)
-        b.synchronize()
-        ms_b = a.elapsed_time(b)
-        fl = 2.0 * m * n * k * per_shape
-        rows.append((lay, m, n, k, ms_pc * 1e3 / per_shape, fl / ms_pc / 1e6, ms_b * 1e3, fl / ms_b / 1e6))
-        if si % 2000 == 0:
-            print("[sweep] %d/%d shapes, %.0fs" % (si, len(shapes), time.time() - t0), file=sys.stderr,
-                  flush=True)
+            def calls():
+                for q in range(q0, q0 + ns):
+                    L.iaat_gemm(ctx.handle, t & 1, t >> 1, m, n, k, 1.0, ao[q], lda, bo[q], ldb, 1.0,
+                                co[q], m, sp)
+            calls()
+            a.record(stream)
+            calls()
+            b.record(stream)
+            b.synchronize()
+            ms_pc = a.elapsed_time(b) / ns
+            dptr = desc.data_ptr() + 64 * q0
+            iaat.iaat_gemm_vbatched_device(ctx.handle, dptr, per_shape, stream=sp)
+            a.record(stream)
+            iaat.iaat_gemm_vbatched_device(ctx.handle, dptr, per_shape, stream=sp)
+            b.record(stream)
+            b.synchronize()
+            ms_b = a.elapsed_time(b)
+            fl = 2.0 * m * n * k
+            rows.append((lay, m, n, k, ms_pc * 1e3, fl / ms_pc / 1e6, ms_b * 1e3,
+                         fl * per_shape / ms_b / 1e6))
+        del buf, desc
+        print("[sweep] %d/%d shapes, %.0fs" % (c0 + len(chunk), len(shapes), time.time() - t0),
+              file=sys.stderr, flush=True)
     ctx.close()
-    os.makedirs(os.path.dirname(os.path.abspath(out_path)), exist_ok=True)
-    with open(out_path, "w") as f:
-        f.write("layout,m,n,k,percall_us,percall_gflops,batched_us,batched_gflops\n")
-        for r in rows:
-            f.write("%s,%d,%d,%d,%.3f,%.3f,%.3f,%.3f\n" % r)
-    summ = {}
+    if out_path:
+        os.makedirs(os.path.dirname(os.path.abspath(out_path)), exist_ok=True)
+        with open(out_path, "w") as f:
+            f.write("layout,m,n,k,percall_us,percall_gflops,batched_us,batched_gflops\n")
+            for r in rows:
+                f.write("%s,%d,%d,%d,%.3f,%.3f,%.3f,%.3f\n" % r)
+    summ = {"per_shape": per_shape, "percall_timed_per_shape": ns, "shapes": len(rows)}
     for lay in ("NN", "NT", "TN", "TT"):
         rr = np.array([r[4:] for r in rows if r[0] == lay])
         summ[lay] = {"shapes": int(rr.shape[0]), "percall_us_median": round(float(np.median(rr[:, 0])), 2),
@@ -332,8 +394,7 @@ def sweep(iaat, inputs, dev, per_shape, out_path):
                      "percall_gflops_max": round(float(np.max(rr[:, 1])), 1),
                      "batched_gflops_median": round(float(np.median(rr[:, 3])), 1),
                      "batched_gflops_max": round(float(np.max(rr[:, 3])), 1)}
-    print(json.dumps({"sweep": summ, "per_shape": per_shape, "csv": out_path}), flush=True)
-    return 0
+    return summ
 
 
 def main() -> int:
@@ -350,12 +411,14 @@ def main() -> int:
     ap.add_argument("--no-percall", action="store_true")
     ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--serve-seconds", type=float, default=1.0,
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="length of each open-loop serving trace (seconds)")
     ap.add_argument("--sweep", action="store_true",
                     help="only the shape sweep: every grid shape, one call per problem vs one "
                          "batched launch; per-shape CSV to --sweep-out, summary JSON to stdout")
-    ap.add_argument("--sweep-per-shape", type=int, default=16)
+    ap.add_argument("--sweep-per-shape", type=int, default=256)
+    ap.add_argument("--no-sweep", action="store_true",
+                    help="skip the shape sweep leg of the default run")
     ap.add_argument("--sweep-out", default="sweep.csv")
     args = ap.parse_args()
 
@@ -381,11 +444,14 @@ def main() -> int:
         return 0
 
     if args.sweep:
-        return sweep(iaat, inputs, dev, args.sweep_per_shape, args.sweep_out)
+        summ = sweep(iaat, inputs, dev, args.sweep_per_shape, args.sweep_out)
+        print(json.dumps({"sweep": summ, "csv": args.sweep_out}), flush=True)
+        return 0
 
     if args.profile:
         args.steps, args.warmup = 5, 1
         args.no_cpu_baseline = args.no_percall = args.no_precision = args.no_serve = True
+        args.no_sweep = True
 
     t0 = time.time()
     ps = inputs.uneven_batch(args.count)
@@ -490,16 +556,19 @@ def main() -> int:
     if not args.no_percall:
         extra["strided_same_size"] = strided_leg(iaat, ctx.handle, dev, stream)
         extra["ablation_traditional"] = traditional_leg(iaat, ctx.handle, ps, desc, ms, dev, stream)
-        extra["dgemm_same_size"] = dgemm_leg(iaat, ctx.handle, dev, stream)
-        extra["cgemm_same_size"] = cgemm_leg(iaat, ctx.handle, dev, stream)
+        for name in ("dgemm", "cgemm", "zgemm"):
+            extra[name] = xgemm_leg(iaat, inputs, ctx.handle, dev, stream, name)
     if not args.no_precision:
         extra["precision"] = precision_leg(iaat, inputs, ctx.handle, dev, stream)
     if not args.no_serve:
         extra["serve"] = serve_leg(iaat, inputs, ctx.handle, dev, args.serve_seconds)
+    if not args.no_sweep:
+        extra["sweep"] = sweep(iaat, inputs, dev, args.sweep_per_shape)
 
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
+        # at most 16 threads: the host CPU share that comes with one GPU
         cores = min(len(os.sched_getaffinity(0)), 16)
         # repeat the full batch until about 1.5 s of wall time (tens of
         # CPU-seconds on the host's cores) so the rate is stable
@@ -510,8 +579,8 @@ def main() -> int:
             reps += 1
         cpu = {"value": round(reps * flops / secs / 1e9, 3), "unit": "GFLOP/s", "cores": cores,
                "kind": "oracle",
-               "sample": "the full %d-problem batch x %d, FP64 triple loop, %d threads, %.2f s"
-                         % (ps.count, reps, cores, secs)}
+               "sample": "the full %d-problem batch x %d, FP64 triple loop, %d threads (the "
+                         "host CPU share of one GPU), %.2f s" % (ps.count, reps, cores, secs)}
 
     iaat.iaat_vbplan_destroy(plan)
     ctx.close()

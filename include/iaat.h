@@ -402,7 +402,9 @@ typedef struct iaat_serve_stats {
 } iaat_serve_stats;
 
 /* Starts a server on the context's device (allocates the arena, streams,
- * pinned staging; starts the scheduler thread).
+ * pinned staging; runs one tiny GEMM per launch slot, so first-use costs of
+ * streams and kernels are paid before the server clock starts; starts the
+ * scheduler thread).
  * Errors: -1 ctx; -2 cfg NULL or out of range; -3 out NULL; IAAT_ERR_NOMEM;
  * IAAT_ERR_HIP. */
 int iaat_serve_start(iaat_ctx_t ctx, const iaat_serve_cfg* cfg, iaat_server_t* out);
@@ -411,8 +413,9 @@ int iaat_serve_start(iaat_ctx_t ctx, const iaat_serve_cfg* cfg, iaat_server_t* o
  * call).  For each GEMM, A and B are device operands and C names the
  * INITIAL value C0 (device, ldc x n, read only when beta != 0; NULL allowed
  * when beta == 0): the result is written to the request's own output region
- * in the arena, GEMM i at float offset out_off(i) = sum over earlier GEMMs
- * of ldc*n rounded up to 64 floats.  `t_arrival` is the request's arrival on
+ * in the arena with the caller's ldc, GEMM i at float offset out_off(i) =
+ * sum over earlier GEMMs of their C span ldc*(n-1)+m rounded up to 64
+ * floats (when beta != 0 only that span of C0 is read).  `t_arrival` is the request's arrival on
  * the server clock (< 0: now); latencies are measured from it.  With
  * keep_output != 0 the output region stays allocated after completion until
  * iaat_serve_release; otherwise it is freed at completion.

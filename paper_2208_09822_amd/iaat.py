@@ -361,9 +361,10 @@ def iaat_serve_stop(srv) -> None:
 
 def out_offsets(gemms: np.ndarray) -> np.ndarray:
     """Float offset of each GEMM's output inside a served request's output
-    region (ldc * n rounded up to 64 floats, in order)."""
+    region (C spans ldc*(n-1)+m, each rounded up to 64 floats, in order)."""
     g = np.asarray(gemms, dtype=PROBLEM_DTYPE)
-    f = np.where((g["m"] > 0) & (g["n"] > 0), g["ldc"].astype(np.int64) * g["n"], 0)
+    f = np.where((g["m"] > 0) & (g["n"] > 0),
+                 g["ldc"].astype(np.int64) * (g["n"].astype(np.int64) - 1) + g["m"], 0)
     f = (f + 63) // 64 * 64
     return np.concatenate([[0], np.cumsum(f)[:-1]]).astype(np.int64)
 

@@ -83,11 +83,13 @@ def test_served_results_equal_alone_results_bitwise(ctx, pool):
             assert st.t_arrival <= st.t_launch <= st.t_done
             g = desc[idx]
             off = iaat.out_offsets(g)
-            total = int(off[-1] + ((int(g["ldc"][-1]) * int(g["n"][-1]) + 63) // 64) * 64)
+            span = lambda i: int(g["ldc"][i]) * (int(g["n"][i]) - 1) + int(g["m"][i])
+            total = int(off[-1] + span(len(g) - 1))
             out = d2h(st.out, total)
             for i, q in enumerate(idx):
                 m, n, ldc = int(ps.m[q]), int(ps.n[q]), int(ps.ldc[q])
-                got = out[off[i]:off[i] + ldc * n].reshape(n, ldc).T[:m, :]
+                col = np.concatenate([out[off[i]:off[i] + span(i)], np.zeros(ldc - m, np.float32)])
+                got = col.reshape(n, ldc).T[:m, :]
                 assert np.array_equal(got.view(np.uint32), alone[int(q)].view(np.uint32)), (q, i)
             iaat.iaat_serve_release(srv, t)
         stats = iaat.iaat_serve_stats_get(srv)
