@@ -405,6 +405,10 @@ def main() -> int:
     ap.add_argument("--count", type=int, default=65536)
     ap.add_argument("--profile", action="store_true",
                     help="short run (5 steps) with no side measurements, for rocprofv3")
+    ap.add_argument("--only", choices=["traditional", "strided", "dgemm", "cgemm", "zgemm",
+                                       "precision"],
+                    help="run one side leg alone (after a single headline step), for profiling; "
+                         "prints that leg's JSON")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device-to-device copy (counter calibration)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -448,8 +452,8 @@ def main() -> int:
         print(json.dumps({"sweep": summ, "csv": args.sweep_out}), flush=True)
         return 0
 
-    if args.profile:
-        args.steps, args.warmup = 5, 1
+    if args.profile or args.only:
+        args.steps, args.warmup = (5, 1) if args.profile else (1, 1)
         args.no_cpu_baseline = args.no_percall = args.no_precision = args.no_serve = True
         args.no_sweep = True
 
@@ -493,6 +497,21 @@ def main() -> int:
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": stored_traffic(workload),
             "kernel": KERNEL, "algorithmic_bytes_per_launch": int(alg_bytes),
             "avg_launch_us": round(ms * 1e3, 2)}
+
+    if args.only:
+        h = ctx.handle
+        if args.only == "traditional":
+            r = traditional_leg(iaat, h, ps, desc, ms, dev, stream)
+        elif args.only == "strided":
+            r = strided_leg(iaat, h, dev, stream)
+        elif args.only == "precision":
+            r = precision_leg(iaat, inputs, h, dev, stream)
+        else:
+            r = xgemm_leg(iaat, inputs, h, dev, stream, args.only)
+        iaat.iaat_vbplan_destroy(plan)
+        ctx.close()
+        print(json.dumps({"only": args.only, "result": r}), flush=True)
+        return 0
 
     extra = {}
     if not args.profile:

@@ -492,6 +492,19 @@ int iaat_family_size(void);
 int iaat_family_info(int kid, int32_t* family, int32_t* p1, int32_t* p2,
                      int32_t* block_rows, int32_t* block_cols);
 
+/* The install-time generator instantiates the family per (shape, layout,
+ * data type) (Section IV, Algorithm 1; Table 1's S, D, C, Z rows).
+ * iaat_family_dtypes writes up to `cap` data-type codes the family is built
+ * for (0 FP32, then IAAT_DT_F64, IAAT_DT_C64, IAAT_DT_C128) and returns how
+ * many there are.  The FP32 batched kernel runs members from LDS in units
+ * (one or two tiles of a grid, up to four rows or columns of a strip, one
+ * row of a K-split block): iaat_staged_unit_count and iaat_staged_unit_info
+ * describe them (family and size parameters as iaat_family_info; -1 for a
+ * unit id out of range). */
+int iaat_family_dtypes(int32_t* codes, int cap);
+int iaat_staged_unit_count(void);
+int iaat_staged_unit_info(int unit, int32_t* family, int32_t* p1, int32_t* p2);
+
 /* 1 if (layout, m, n, k) is in the small-GEMM domain (MNK <= 80^3, or
  * <= 32^3 for TN, evaluated in exact integers), else 0; -i for a bad
  * argument. */

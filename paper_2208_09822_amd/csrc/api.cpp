@@ -705,6 +705,32 @@ int iaat_table_save(iaat_ctx_t ctx, const char* path) {
 
 int iaat_family_size(void) { return IAAT_NUM_KIDS; }
 
+int iaat_family_dtypes(int32_t* codes, int cap) {
+  static const int32_t kCodes[IAAT_NUM_DTYPES] = {
+#define IAAT_DT_CODE(code, letter) code,
+      IAAT_FOR_EACH_DTYPE(IAAT_DT_CODE)
+#undef IAAT_DT_CODE
+  };
+  if (codes)
+    for (int i = 0; i < IAAT_NUM_DTYPES && i < cap; ++i) codes[i] = kCodes[i];
+  return IAAT_NUM_DTYPES;
+}
+
+int iaat_staged_unit_count(void) { return IAAT_NUM_STAGED_UNITS; }
+
+int iaat_staged_unit_info(int unit, int32_t* family, int32_t* p1, int32_t* p2) {
+  static const int32_t kUnits[IAAT_NUM_STAGED_UNITS][3] = {
+#define IAAT_UNIT_INFO(uid, fam, a, b) {fam, a, b},
+      IAAT_FOR_EACH_STAGED_UNIT(IAAT_UNIT_INFO)
+#undef IAAT_UNIT_INFO
+  };
+  if (unit < 0 || unit >= IAAT_NUM_STAGED_UNITS) return fail(-1, "iaat_staged_unit_info: unit=%d", unit);
+  if (family) *family = kUnits[unit][0];
+  if (p1) *p1 = kUnits[unit][1];
+  if (p2) *p2 = kUnits[unit][2];
+  return IAAT_OK;
+}
+
 int iaat_family_info(int kid, int32_t* family, int32_t* p1, int32_t* p2, int32_t* block_rows,
                      int32_t* block_cols) {
   if (kid < 0 || kid >= IAAT_NUM_KIDS) return fail(-1, "iaat_family_info: kid=%d", kid);

@@ -427,25 +427,37 @@ struct StagedKred {
 //   U_KRED + c - 1    K-split block of 1 row x c = 1..4 columns
 // Few, small units keep the compute loop's code within the instruction
 // cache.
-enum { U_TILE = 0, U_TILE2 = 1, U_ROWS = 2, U_COLS = 6, U_KRED = 10, U_COUNT = 14 };
+// Unit ids, from the generated list (IAAT_FOR_EACH_STAGED_UNIT).
+enum {
+  U_TILE = IAAT_U_TILE,
+  U_TILE2 = IAAT_U_TILE2,
+  U_ROWS = IAAT_U_ROWS,
+  U_COLS = IAAT_U_COLS,
+  U_KRED = IAAT_U_KRED,
+  U_COUNT = IAAT_NUM_STAGED_UNITS
+};
+
+// The staged routine of a generated unit (family, p1, p2).
+template <int FAM, int TA, int TB, int P1, int P2, bool CMEM>
+struct StagedUnit;
+template <int TA, int TB, int P1, int P2, bool CMEM>
+struct StagedUnit<0, TA, TB, P1, P2, CMEM> : StagedMfma<TA, TB, P1, P2, CMEM> {};
+template <int TA, int TB, int P1, int P2, bool CMEM>
+struct StagedUnit<1, TA, TB, P1, P2, CMEM> : StagedRows<TA, TB, P1, CMEM> {};
+template <int TA, int TB, int P1, int P2, bool CMEM>
+struct StagedUnit<2, TA, TB, P1, P2, CMEM> : StagedCols<TA, TB, P2, CMEM> {};
+template <int TA, int TB, int P1, int P2, bool CMEM>
+struct StagedUnit<3, TA, TB, P1, P2, CMEM> : StagedKred<TA, TB, P1, P2, CMEM> {};
 
 template <int TA, int TB, bool CMEM>
 __device__ __forceinline__ void unit_body(int u, const SProb& P, int i0, int j0) {
   switch (u) {
-    case U_TILE: StagedMfma<TA, TB, 1, 1, CMEM>::run(P, i0, j0); break;
-    case U_TILE2: StagedMfma<TA, TB, 1, 2, CMEM>::run(P, i0, j0); break;
-    case U_ROWS + 0: StagedRows<TA, TB, 1, CMEM>::run(P, i0, j0); break;
-    case U_ROWS + 1: StagedRows<TA, TB, 2, CMEM>::run(P, i0, j0); break;
-    case U_ROWS + 2: StagedRows<TA, TB, 3, CMEM>::run(P, i0, j0); break;
-    case U_ROWS + 3: StagedRows<TA, TB, 4, CMEM>::run(P, i0, j0); break;
-    case U_COLS + 0: StagedCols<TA, TB, 1, CMEM>::run(P, i0, j0); break;
-    case U_COLS + 1: StagedCols<TA, TB, 2, CMEM>::run(P, i0, j0); break;
-    case U_COLS + 2: StagedCols<TA, TB, 3, CMEM>::run(P, i0, j0); break;
-    case U_COLS + 3: StagedCols<TA, TB, 4, CMEM>::run(P, i0, j0); break;
-    case U_KRED + 0: StagedKred<TA, TB, 1, 1, CMEM>::run(P, i0, j0); break;
-    case U_KRED + 1: StagedKred<TA, TB, 1, 2, CMEM>::run(P, i0, j0); break;
-    case U_KRED + 2: StagedKred<TA, TB, 1, 3, CMEM>::run(P, i0, j0); break;
-    case U_KRED + 3: StagedKred<TA, TB, 1, 4, CMEM>::run(P, i0, j0); break;
+#define IAAT_UNIT_CASE(uid, fam, p1, p2)                      \
+  case uid:                                                  \
+    StagedUnit<fam, TA, TB, p1, p2, CMEM>::run(P, i0, j0); \
+    break;
+    IAAT_FOR_EACH_STAGED_UNIT(IAAT_UNIT_CASE)
+#undef IAAT_UNIT_CASE
     default:
       break;
   }

@@ -152,6 +152,9 @@ def lib():
                 "iaat_default_plan": (i32, [i32, i32, i32, ctypes.POINTER(IaatBlock), i32]),
                 "iaat_family_size": (i32, []),
                 "iaat_family_info": (i32, [i32] + [ctypes.POINTER(ctypes.c_int32)] * 5),
+                "iaat_family_dtypes": (i32, [vp, i32]),
+                "iaat_staged_unit_count": (i32, []),
+                "iaat_staged_unit_info": (i32, [i32] + [ctypes.POINTER(ctypes.c_int32)] * 3),
                 "iaat_in_small_domain": (i32, [i32, i64, i64, i64]),
             }
             for name, (res, args) in sig.items():
@@ -424,6 +427,22 @@ def iaat_family_info(kid: int):
     _check(lib().iaat_family_info(int(kid), *[ctypes.byref(v) for v in vals]))
     fam, p1, p2, br, bc = (v.value for v in vals)
     return {"family": FAMILY_NAMES[fam], "p1": p1, "p2": p2, "rows": br, "cols": bc}
+
+
+def iaat_family_dtypes():
+    n = lib().iaat_family_dtypes(None, 0)
+    arr = (ctypes.c_int32 * n)()
+    lib().iaat_family_dtypes(arr, n)
+    return list(arr)
+
+
+def iaat_staged_units():
+    out = []
+    for u in range(lib().iaat_staged_unit_count()):
+        vals = [ctypes.c_int32() for _ in range(3)]
+        _check(lib().iaat_staged_unit_info(u, *[ctypes.byref(v) for v in vals]))
+        out.append((FAMILY_NAMES[vals[0].value], vals[1].value, vals[2].value))
+    return out
 
 
 def iaat_in_small_domain(layout, m, n, k) -> bool:

@@ -55,6 +55,15 @@ def test_small_domain_predicate_edges():
         d(4, 1, 1, 1)
 
 
+def test_generated_registry_matches_library():
+    # the data types and staged units the library dispatches are exactly the
+    # generator's lists
+    assert iaat.iaat_family_dtypes() == [code for code, _ in gen_family.DTYPES]
+    assert iaat.iaat_staged_units() == [(fam, p1, p2) for _, fam, p1, p2 in gen_family.staged_units()]
+    assert iaat.lib().iaat_staged_unit_info(iaat.lib().iaat_staged_unit_count(), None, None,
+                                            None) == -1
+
+
 def test_family_matches_generator():
     kids = gen_family.family()
     assert iaat.iaat_family_size() == len(kids)
