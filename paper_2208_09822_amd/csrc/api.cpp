@@ -98,8 +98,9 @@ hipError_t launch_batch(iaat_ctx_t ctx, const iaat_problem* probs_dev, int64_t c
                         int32_t* status, hipStream_t s, uint32_t* ticket) {
   VbArgs a{probs_dev, count, status, ctx->table_dev, ticket};
   if (prec != IAAT_PREC_F32) {
-    const int64_t cap = 8LL * ctx->num_cu;  // work-groups of 256 threads, grid-stride over problems
-    return launch_vbatched_lowp(a, prec, (int)(count < cap ? count : cap), s);
+    // work-groups of four wavefronts, one problem per wavefront (grid-stride)
+    const int64_t cap = 8LL * ctx->num_cu, need = (count + 3) / 4;
+    return launch_vbatched_lowp(a, prec, (int)(need < cap ? need : cap), s);
   }
   // work-groups take 4-problem windows
   const int64_t units = (count + 3) / 4;

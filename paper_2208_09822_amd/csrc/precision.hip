@@ -113,17 +113,34 @@ __device__ uint32_t block_absmax_bits(const float* x, int64_t n, uint32_t* red) 
   return r;
 }
 
+// Four 16-bit codes of four floats, 16-byte loads and 8-byte stores where
+// source and destination allow it (the encoders run per element either way).
+template <class Enc>
+__device__ __forceinline__ void encode16(const float* src, uint16_t* d, int64_t n, Enc enc) {
+  int64_t i0 = 0;
+  if ((((uintptr_t)src & 15) == 0) && (((uintptr_t)d & 7) == 0)) {
+    const int64_t n4 = n >> 2;
+    const float4* s4 = (const float4*)src;
+    uint2* d4 = (uint2*)d;
+    for (int64_t i = threadIdx.x; i < n4; i += blockDim.x) {
+      const float4 v = s4[i];
+      d4[i] = uint2{(uint32_t)enc(v.x) | ((uint32_t)enc(v.y) << 16),
+                    (uint32_t)enc(v.z) | ((uint32_t)enc(v.w) << 16)};
+    }
+    i0 = n4 << 2;
+  }
+  for (int64_t i = i0 + threadIdx.x; i < n; i += blockDim.x) d[i] = enc(src[i]);
+}
+
 // One operand of one job: returns the scale exponent used (FP8) or 0.
 __device__ int quantize_operand(int prec, const float* src, void* dst, int64_t n, uint32_t* red) {
   if (n <= 0) return 0;
   if (prec == IAAT_PREC_BF16) {
-    uint16_t* d = (uint16_t*)dst;
-    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) d[i] = to_bf16(src[i]);
+    encode16(src, (uint16_t*)dst, n, [](float x) { return to_bf16(x); });
     return 0;
   }
   if (prec == IAAT_PREC_F16) {
-    uint16_t* d = (uint16_t*)dst;
-    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) d[i] = to_f16(src[i]);
+    encode16(src, (uint16_t*)dst, n, [](float x) { return to_f16(x); });
     return 0;
   }
   if (prec == IAAT_PREC_BF16X3) {  // hi = bf16(x) in [0, n), lo = bf16(x - hi) in [n, 2n)
@@ -170,21 +187,28 @@ __device__ __forceinline__ T ld_el(const T* X, int64_t r, int64_t c, int64_t ld)
 }
 
 // Fragment of op(A) for one 16 x 16 tile step: KW consecutive k values of
-// row i (k >= K give code 0, which is +0 in every format).
-template <typename T, int KW, int TA>
+// row i (with TAIL, k >= K give code 0, which is +0 in every format; full
+// chunks skip the test).
+template <typename T, int KW, int TA, bool TAIL>
 __device__ __forceinline__ void frag_a(const T* A, int64_t lda, int i, int k0, int K, T* out) {
 #pragma unroll
   for (int e = 0; e < KW; ++e) {
     const int k = k0 + e;
-    out[e] = k < K ? (TA ? ld_el(A, k, i, lda) : ld_el(A, i, k, lda)) : (T)0;
+    if (TAIL)
+      out[e] = k < K ? (TA ? ld_el(A, k, i, lda) : ld_el(A, i, k, lda)) : (T)0;
+    else
+      out[e] = TA ? ld_el(A, k, i, lda) : ld_el(A, i, k, lda);
   }
 }
-template <typename T, int KW, int TB>
+template <typename T, int KW, int TB, bool TAIL>
 __device__ __forceinline__ void frag_b(const T* B, int64_t ldb, int j, int k0, int K, T* out) {
 #pragma unroll
   for (int e = 0; e < KW; ++e) {
     const int k = k0 + e;
-    out[e] = k < K ? (TB ? ld_el(B, j, k, ldb) : ld_el(B, k, j, ldb)) : (T)0;
+    if (TAIL)
+      out[e] = k < K ? (TB ? ld_el(B, j, k, ldb) : ld_el(B, k, j, ldb)) : (T)0;
+    else
+      out[e] = TB ? ld_el(B, j, k, ldb) : ld_el(B, k, j, ldb);
   }
 }
 
@@ -204,15 +228,15 @@ __device__ __forceinline__ uint16_t e4m3_to_f16(uint8_t c) {
 
 // Products of one 16-wide k-step of a 16 x 16 tile.  Lane l supplies row
 // l%16 of op(A) and column l%16 of op(B) at k = k0 + 4*(l/16) + 0..3.
-template <int PREC, int TA, int TB>
+template <int PREC, int TA, int TB, bool TAIL>
 __device__ __forceinline__ f4v tile_step(const void* Av, const void* Bv, int64_t lda, int64_t ldb,
                                          int64_t a_lo, int64_t b_lo, int i, int j, int k0, int K,
                                          f4v acc) {
   const int g = (int)(threadIdx.x & 63) >> 4;
   if constexpr (PREC == IAAT_PREC_F8E4M3) {
     uint8_t a[4], b[4];
-    frag_a<uint8_t, 4, TA>((const uint8_t*)Av, lda, i, k0 + 4 * g, K, a);
-    frag_b<uint8_t, 4, TB>((const uint8_t*)Bv, ldb, j, k0 + 4 * g, K, b);
+    frag_a<uint8_t, 4, TA, TAIL>((const uint8_t*)Av, lda, i, k0 + 4 * g, K, a);
+    frag_b<uint8_t, 4, TB, TAIL>((const uint8_t*)Bv, ldb, j, k0 + 4 * g, K, b);
     h4v va, vb;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
@@ -224,8 +248,8 @@ __device__ __forceinline__ f4v tile_step(const void* Av, const void* Bv, int64_t
     uint16_t a[4], b[4];
     const uint16_t* A = (const uint16_t*)Av;
     const uint16_t* B = (const uint16_t*)Bv;
-    frag_a<uint16_t, 4, TA>(A, lda, i, k0 + 4 * g, K, a);
-    frag_b<uint16_t, 4, TB>(B, ldb, j, k0 + 4 * g, K, b);
+    frag_a<uint16_t, 4, TA, TAIL>(A, lda, i, k0 + 4 * g, K, a);
+    frag_b<uint16_t, 4, TB, TAIL>(B, ldb, j, k0 + 4 * g, K, b);
     if constexpr (PREC == IAAT_PREC_F16) {
       h4v va, vb;
 #pragma unroll
@@ -244,8 +268,8 @@ __device__ __forceinline__ f4v tile_step(const void* Av, const void* Bv, int64_t
       if constexpr (PREC == IAAT_PREC_BF16X3) {
         // small terms first: lo*hi + hi*lo, then hi*hi
         uint16_t al[4], bl[4];
-        frag_a<uint16_t, 4, TA>(A + a_lo, lda, i, k0 + 4 * g, K, al);
-        frag_b<uint16_t, 4, TB>(B + b_lo, ldb, j, k0 + 4 * g, K, bl);
+        frag_a<uint16_t, 4, TA, TAIL>(A + a_lo, lda, i, k0 + 4 * g, K, al);
+        frag_b<uint16_t, 4, TB, TAIL>(B + b_lo, ldb, j, k0 + 4 * g, K, bl);
         s4v val, vbl;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
@@ -260,25 +284,28 @@ __device__ __forceinline__ f4v tile_step(const void* Av, const void* Bv, int64_t
   }
 }
 
-// One problem on one work-group of four wavefronts: C is covered by 16 x 16
-// matrix-core tiles, dealt round-robin to the wavefronts; each tile runs the
-// whole K, then the FP32 epilogue.
+// One problem on one wavefront: C is covered by 16 x 16 matrix-core tiles,
+// taken in turn; each tile runs the whole K (full 16-wide chunks without a
+// K test, then the partial chunk), then the FP32 epilogue.
 template <int PREC, int TA, int TB>
 __device__ void lowp_problem(const iaat_problem& P) {
   const int KS = 16;
-  const int l = (int)(threadIdx.x & 63), w = (int)(threadIdx.x >> 6);
+  const int l = (int)(threadIdx.x & 63);
   const int m = P.m, n = P.n, K = P.k;
   const int64_t lda = P.lda, ldb = P.ldb, ldc = P.ldc;
   // the lo halves of split operands follow the hi matrices
   const int64_t a_lo = lda * (TA ? m : K), b_lo = ldb * (TB ? K : n);
   const float alpha = P.alpha * P.ab_scale, beta = P.beta;
   const int tm = (m + 15) >> 4, tn = (n + 15) >> 4;
-  for (int t = w; t < tm * tn; t += 4) {
+  const int kfull = K & ~(KS - 1);
+  for (int t = 0; t < tm * tn; ++t) {
     const int i0 = 16 * (t % tm), j0 = 16 * (t / tm);
     const int i = min(i0 + (l & 15), m - 1), j = min(j0 + (l & 15), n - 1);
     f4v acc = {0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < K; k0 += KS)
-      acc = tile_step<PREC, TA, TB>(P.A, P.B, lda, ldb, a_lo, b_lo, i, j, k0, K, acc);
+    for (int k0 = 0; k0 < kfull; k0 += KS)
+      acc = tile_step<PREC, TA, TB, false>(P.A, P.B, lda, ldb, a_lo, b_lo, i, j, k0, K, acc);
+    if (kfull < K)
+      acc = tile_step<PREC, TA, TB, true>(P.A, P.B, lda, ldb, a_lo, b_lo, i, j, kfull, K, acc);
     const int jc = j0 + (l & 15);
     if (jc < n) {
 #pragma unroll
@@ -293,15 +320,20 @@ __device__ void lowp_problem(const iaat_problem& P) {
   }
 }
 
+// Wavefront w of the grid (four per work-group) takes problems w, w + W, ...
+// (W wavefronts in all): small problems keep every wavefront busy.
 template <int PREC>
 __global__ __launch_bounds__(256) void vbatched_lowp_kernel(VbArgs a) {
-  for (int64_t q = blockIdx.x; q < a.count; q += gridDim.x) {
+  const int64_t W = (int64_t)gridDim.x * 4;
+  const int64_t w0 = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int l = (int)(threadIdx.x & 63);
+  for (int64_t q = w0; q < a.count; q += W) {
     const iaat_problem P = a.probs[q];
     const int st = validate(P.trans, P.m, P.n, P.k, P.lda, P.ldb, P.ldc, P.alpha, P.A, P.B, P.C);
-    if (threadIdx.x == 0 && a.status != nullptr) a.status[q] = st;
+    if (l == 0 && a.status != nullptr) a.status[q] = st;
     if (st != 0 || P.m == 0 || P.n == 0) continue;
     if (P.alpha == 0.0f || P.k == 0) {  // C = beta*C, A and B not read
-      for (int64_t e = threadIdx.x; e < (int64_t)P.m * P.n; e += blockDim.x) {
+      for (int64_t e = l; e < (int64_t)P.m * P.n; e += 64) {
         float* c = P.C + e % P.m + (e / P.m) * (int64_t)P.ldc;
         *c = P.beta == 0.0f ? 0.0f : P.beta * *c;
       }
