@@ -302,8 +302,8 @@ int iaat_quantize_batch(iaat_ctx_t ctx, int prec, const iaat_qjob* jobs_dev, int
  * iaat_vbplan_create allocates and synchronises the device; launch does
  * neither.
  * create errors: -1 ctx, -2 probs_dev, -3 count, -4 prec, -6 out.
- * An FP32 plan hands the 4-problem windows out to work-groups dynamically
- * from a counter the plan owns (cleared by a kernel at the start of each
+ * An FP32 plan hands windows of consecutive problems out to work-groups
+ * dynamically from a counter the plan owns (cleared by a kernel at the start of each
  * replay), so replays of ONE plan must not overlap: launch them on one
  * stream, or wait between them.
  */
@@ -312,9 +312,28 @@ int iaat_vbplan_create(iaat_ctx_t ctx, const iaat_problem* probs_dev, int64_t co
 int iaat_vbplan_launch(iaat_vbplan_t plan, iaat_stream_t stream);
 int iaat_vbplan_destroy(iaat_vbplan_t plan); /* NULL accepted */
 
+/* Graph-replayed batches from HOST descriptors (Section V-B's executing
+ * plan, replayed): iaat_vbatched_plan reserves pinned host staging and a
+ * device descriptor array for up to `capacity` problems of precision `prec`;
+ * iaat_vbatched_run copies `count` <= capacity host descriptors into the
+ * pinned staging (after the plan's previous run has read it) and replays a
+ * HIP graph holding the host-to-device descriptor copy and the batched
+ * launch, captured again only when `count` differs from the previous run.
+ * Per-problem argument errors are not reported (use the device-descriptor
+ * forms with a status array for that); invalid problems are skipped.  Runs
+ * of one plan must be issued on one stream, or waited for in between.
+ * plan errors: -1 ctx, -2 capacity (< 1 or > 2^31-1), -3 prec, -4 out;
+ * run errors: -1 plan, -2 probs NULL with count > 0, -3 count out of
+ * [0, capacity].  iaat_vbatched_free accepts NULL. */
+typedef struct iaat_hplan* iaat_hplan_t;
+int iaat_vbatched_plan(iaat_ctx_t ctx, int64_t capacity, int prec, iaat_hplan_t* out);
+int iaat_vbatched_run(iaat_hplan_t plan, const iaat_problem* probs_host, int64_t count,
+                      iaat_stream_t stream);
+int iaat_vbatched_free(iaat_hplan_t plan);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the FP32
- * batched launch of iaat_vbplan_* (4-problem windows handed out to
+ * batched launch of iaat_vbplan_* (windows of problems handed out to
  * work-groups from a counter, which balances uneven batches) without a plan
  * object.  The counter lives in a fixed 256-byte array of device memory that
  * the library holds on each GPU until the process ends; its address is

@@ -592,6 +592,91 @@ int iaat_vbplan_destroy(iaat_vbplan_t plan) {
   return IAAT_OK;
 }
 
+int iaat_vbatched_plan(iaat_ctx_t ctx, int64_t capacity, int prec, iaat_hplan_t* out) {
+  if (!ctx) return fail(-1, "iaat_vbatched_plan: ctx is NULL");
+  if (capacity < 1 || capacity > 0x7fffffffLL)
+    return fail(-2, "iaat_vbatched_plan: capacity=%lld", (long long)capacity);
+  if (prec < IAAT_PREC_F32 || prec > IAAT_PREC_BF16X3) return fail(-3, "iaat_vbatched_plan: prec=%d", prec);
+  if (!out) return fail(-4, "iaat_vbatched_plan: out is NULL");
+  *out = nullptr;
+  DeviceGuard g(ctx->device);
+  iaat_hplan* p = new iaat_hplan;
+  p->ctx = ctx;
+  p->prec = prec;
+  p->capacity = capacity;
+  const size_t bytes = (size_t)capacity * sizeof(iaat_problem);
+  hipError_t e = hipHostMalloc((void**)&p->host, bytes, 0);
+  if (e == hipSuccess) e = hipMalloc((void**)&p->dev, bytes);
+  if (e == hipSuccess && prec == IAAT_PREC_F32) e = hipMalloc((void**)&p->ticket, 256);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&p->done, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    iaat_vbatched_free(p);
+    return fail(IAAT_ERR_NOMEM, "iaat_vbatched_plan: %lld descriptors", (long long)capacity);
+  }
+  *out = p;
+  return IAAT_OK;
+}
+
+// Captures the descriptor upload and the batched launch for `count` problems.
+static hipError_t hplan_capture(iaat_hplan* p, int64_t count) {
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  p->exec = nullptr;
+  p->graph = nullptr;
+  p->count = -1;
+  hipStream_t cs = nullptr;
+  hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    if (cs) (void)hipStreamDestroy(cs);
+    return e;
+  }
+  hipError_t le = hipSuccess;
+  if (count > 0) {
+    le = hipMemcpyAsync(p->dev, p->host, (size_t)count * sizeof(iaat_problem), hipMemcpyHostToDevice, cs);
+    if (le == hipSuccess) le = launch_batch(p->ctx, p->dev, count, p->prec, nullptr, cs, p->ticket);
+  }
+  e = hipStreamEndCapture(cs, &p->graph);
+  (void)hipStreamDestroy(cs);
+  if (le != hipSuccess) return le;
+  if (e == hipSuccess) e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+  if (e == hipSuccess) p->count = count;
+  return e;
+}
+
+int iaat_vbatched_run(iaat_hplan_t p, const iaat_problem* probs_host, int64_t count,
+                      iaat_stream_t stream) {
+  if (!p) return fail(-1, "iaat_vbatched_run: plan is NULL");
+  if (count < 0 || count > p->capacity)
+    return fail(-3, "iaat_vbatched_run: count=%lld outside [0, %lld]", (long long)count,
+                (long long)p->capacity);
+  if (count > 0 && !probs_host) return fail(-2, "iaat_vbatched_run: probs is NULL");
+  DeviceGuard g(p->ctx->device);
+  // the previous replay's upload has read the staging once this event is done
+  hipError_t e = hipEventSynchronize(p->done);
+  if (e != hipSuccess) return hip_fail(e, "iaat_vbatched_run: wait");
+  if (count > 0) memcpy(p->host, probs_host, (size_t)count * sizeof(iaat_problem));
+  if (count != p->count && (e = hplan_capture(p, count)) != hipSuccess)
+    return hip_fail(e, "iaat_vbatched_run: capture");
+  e = hipGraphLaunch(p->exec, (hipStream_t)stream);
+  if (e == hipSuccess) e = hipEventRecord(p->done, (hipStream_t)stream);
+  return e == hipSuccess ? IAAT_OK : hip_fail(e, "iaat_vbatched_run: launch");
+}
+
+int iaat_vbatched_free(iaat_hplan_t p) {
+  if (!p) return IAAT_OK;
+  DeviceGuard g(p->ctx->device);
+  if (p->done) (void)hipEventSynchronize(p->done);
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->ticket) (void)hipFree(p->ticket);
+  if (p->dev) (void)hipFree(p->dev);
+  if (p->host) (void)hipHostFree(p->host);
+  if (p->done) (void)hipEventDestroy(p->done);
+  delete p;
+  return IAAT_OK;
+}
+
 int iaat_gemm_vbatched(iaat_ctx_t ctx, const iaat_problem* probs_host, int64_t count, int prec,
                        int32_t* status, iaat_stream_t stream) {
   if (!ctx) return fail(-1, "iaat_gemm_vbatched: ctx is NULL");

@@ -16,6 +16,19 @@ struct iaat_vbplan {
   int64_t count = 0;
 };
 
+struct iaat_hplan {
+  iaat_ctx* ctx = nullptr;
+  int prec = 0;
+  int64_t capacity = 0;
+  iaat_problem* host = nullptr;  // pinned staging
+  iaat_problem* dev = nullptr;
+  uint32_t* ticket = nullptr;    // FP32 window counter
+  hipEvent_t done = nullptr;     // the last replay
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int64_t count = -1;            // problems the graph was captured for
+};
+
 struct iaat_ctx {
   int device = 0;
   int num_cu = 0;

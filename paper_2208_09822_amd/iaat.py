@@ -128,6 +128,9 @@ def lib():
                 "iaat_zgemm_strided_batched": (i32, [vp, i32, i32, i64, i64, i64, vp, vp, i64, i64,
                                                      vp, i64, i64, vp, vp, i64, i64, i64, vp]),
                 "iaat_xgemm_vbatched": (i32, [vp, i32, vp, i64, vp, vp]),
+                "iaat_vbatched_plan": (i32, [vp, i64, i32, ctypes.POINTER(vp)]),
+                "iaat_vbatched_run": (i32, [vp, vp, i64, vp]),
+                "iaat_vbatched_free": (i32, [vp]),
                 "iaat_trad_pack": (i32, [vp, vp]),
                 "iaat_trad_compute": (i32, [vp, vp]),
                 "iaat_trad_workspace_bytes": (i64, [vp]),
@@ -278,6 +281,22 @@ assert XPROBLEM_DTYPE.itemsize == 96
 def iaat_xgemm_vbatched(ctx, dtype, probs_dev, count, status_dev=0, stream=0) -> None:
     _check(lib().iaat_xgemm_vbatched(ctx, dtype, probs_dev or None, count, status_dev or None,
                                      stream or None))
+
+
+def iaat_vbatched_plan(ctx, capacity, prec=IAAT_PREC_F32) -> int:
+    h = ctypes.c_void_p()
+    _check(lib().iaat_vbatched_plan(ctx, int(capacity), int(prec), ctypes.byref(h)))
+    return h.value
+
+
+def iaat_vbatched_run(plan, probs_host: np.ndarray, stream=0) -> None:
+    d = np.ascontiguousarray(probs_host, dtype=PROBLEM_DTYPE)
+    _check(lib().iaat_vbatched_run(plan, d.ctypes.data if d.shape[0] else None, d.shape[0],
+                                   stream or None))
+
+
+def iaat_vbatched_free(plan) -> None:
+    _check(lib().iaat_vbatched_free(plan))
 
 
 def iaat_trad_create(ctx, probs_host: np.ndarray) -> int:
