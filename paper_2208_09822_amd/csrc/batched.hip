@@ -487,9 +487,9 @@ __device__ __forceinline__ void run_unit(int u, const SProb& P, int i0, int j0) 
 // so each step's latency hides behind a batch's copies.  Every
 // wavefront copies its share of the batch's A, B and (when beta != 0) C
 // spans verbatim into LDS with memory-to-LDS loads; after one wait,
-// wavefronts 1..7 take the batch's units one at a time from a shared counter
-// and run them from LDS, storing C, while wavefront 0 packs the next batch.  A barrier closes the iteration
-// because the buffer is refilled.  Problems that do not fit the buffer are
+// wavefronts 1..7 run the batch's units round-robin (longest first) from
+// LDS, storing C, while wavefront 0 packs the next batch.  A barrier closes
+// the iteration because the buffer is refilled.  Problems that do not fit the buffer are
 // left to vbatched_direct_kernel; quick returns and status codes are handled
 // here.
 
@@ -523,7 +523,6 @@ __shared__ __attribute__((aligned(16))) BatchProb g_bprob[2][kMaxBatch];
 // single tiles) from the front, the single tiles from the back, so the
 // compute wavefronts take the longest first and the batch ends evenly
 __shared__ uint32_t g_bunit[2][kMaxUnits];
-__shared__ int g_bnext[2];                  // the compute wavefronts' unit counters
 __shared__ CopyJob g_copy[2][3 * kMaxBatch];
 __shared__ int g_bhead[2][4];  // problems, units, long units, more-to-come
 
@@ -930,7 +929,6 @@ __device__ __forceinline__ void pack_batch(const VbArgs& a, const WinShape& z, W
     g_bhead[tb][1] = nb;
     g_bhead[tb][2] = nlong;
     g_bhead[tb][3] = more ? 1 : 0;
-    g_bnext[tb] = 0;
   }
 }
 
@@ -944,21 +942,20 @@ __device__ __forceinline__ uint32_t rfl(uint32_t v) {
   return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
 }
 
-// A compute wavefront takes the batch's units one at a time from the shared
-// counter (the next one claimed before the current one runs, so the claim's
-// latency is hidden) and runs each from the staged operands.
-__device__ __forceinline__ void compute_batch(int t, lds_f* stage, int nb, int nlong) {
+// Compute wavefront w (1..7) runs units w - 1, w + 6, w + 13, ... of the
+// batch's longest-first unit list (a static round-robin: no claim round
+// trip), reading the next unit word while the current unit runs.
+__device__ __forceinline__ void compute_batch(int t, lds_f* stage, int nb, int nlong, int w) {
   const int gap = kMaxUnits - nb;  // unit b >= nlong sits at b + gap
-  int b = 0;
-  if (lane() == 0) b = atomicAdd(&g_bnext[t], 1);
-  b = uni(b);
+  // static round-robin over the longest-first list: unit b to compute
+  // wavefront (b mod 7); the next unit word is read while a unit runs
+  int b = w - 1;
+  uint32_t e_next = b < nb ? g_bunit[t][b < nlong ? b : b + gap] : 0u;
   while (b < nb) {
-    int bn = 0;
-    if (lane() == 0) bn = atomicAdd(&g_bnext[t], 1);
-    const uint32_t e = rfl(g_bunit[t][b < nlong ? b : b + gap]);
+    const uint32_t e = rfl(e_next);
+    const int bn = b + (kWaves - 1);
+    e_next = bn < nb ? g_bunit[t][bn < nlong ? bn : bn + gap] : 0u;
     const int u = (int)((e >> 16) & 0xff), i0 = (int)(e & 0xff), j0 = (int)((e >> 8) & 0xff);
-    // the problem entry (64 bytes: C, la, lb, lc, m, n, k, lda, ldb, ldc,
-    // alpha, beta, trans): four 16-byte reads, made scalar
     const u4* pe = reinterpret_cast<const u4*>(&g_bprob[t][e >> 24]);
     const u4 w0 = pe[0], w1 = pe[1], w2 = pe[2], w3 = pe[3];
     float* C = (float*)(((uint64_t)rfl(w0.y) << 32) | rfl(w0.x));
@@ -975,7 +972,7 @@ __device__ __forceinline__ void compute_batch(int t, lds_f* stage, int nb, int n
       case 2: run_unit<0, 1>(u, P, i0, j0); break;
       default: run_unit<1, 1>(u, P, i0, j0); break;
     }
-    b = uni(bn);
+    b = bn;
   }
 }
 
@@ -1048,7 +1045,7 @@ __device__ __forceinline__ void compute_loop(int w, lds_f* stage) {
     const int nlong = uni(g_bhead[t][2]);
     issue_copies(t, w, stage);
     staged_barrier();  // batch t has landed
-    if (np > 0) compute_batch(t, stage, nb, nlong);
+    if (np > 0) compute_batch(t, stage, nb, nlong, w);
     if (!more) break;
     __syncthreads();
   }
