@@ -406,7 +406,7 @@ def main() -> int:
     ap.add_argument("--profile", action="store_true",
                     help="short run (5 steps) with no side measurements, for rocprofv3")
     ap.add_argument("--only", choices=["traditional", "strided", "dgemm", "cgemm", "zgemm",
-                                       "precision"],
+                                       "precision", "serve"],
                     help="run one side leg alone (after a single headline step), for profiling; "
                          "prints that leg's JSON")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -506,6 +506,8 @@ def main() -> int:
             r = strided_leg(iaat, h, dev, stream)
         elif args.only == "precision":
             r = precision_leg(iaat, inputs, h, dev, stream)
+        elif args.only == "serve":
+            r = serve_leg(iaat, inputs, h, dev, args.serve_seconds)
         else:
             r = xgemm_leg(iaat, inputs, h, dev, stream, args.only)
         iaat.iaat_vbplan_destroy(plan)
