@@ -438,13 +438,19 @@ def main() -> int:
 
     dev = torch.device("cuda:0")
     if args.calibrate_copy:
+        # two reference kernels of known traffic: a 1 GiB device copy (reads
+        # 1 GiB, writes 1 GiB) and an elementwise add (reads 2 GiB, writes 1 GiB)
         n = (1 << 30) // 4
         src = torch.ones(n, dtype=torch.float32, device=dev)
+        src2 = torch.full((n,), 2.0, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
         for _ in range(3):
             dst.copy_(src)
+        for _ in range(3):
+            torch.add(src, src2, out=dst)
         torch.cuda.synchronize()
-        print(json.dumps({"calibrate_copy_bytes": 1 << 30, "launches": 3}))
+        print(json.dumps({"calibrate_copy_bytes": 1 << 30, "launches": 3,
+                          "calibrate_add_read_bytes": 2 << 30, "add_launches": 3}))
         return 0
 
     if args.sweep:

@@ -28,38 +28,60 @@ def stored(lay, m, n, k):
     return ta, tb, ra, ca, rb, cb
 
 
+def strided_set(ta, tb, m, n, k, ra, rb, sa, sb, sc, batch, al, be, A, B, C):
+    """The strided batch as a problem set over one buffer (A, B, C back to
+    back), for the oracle's batch driver."""
+    z = np.arange(batch, dtype=np.int64)
+    na, nb = sa * batch, sb * batch
+    full = lambda v, t: np.full(batch, v, dtype=t)
+    return inputs.ProblemSet(full(int(ta) | (int(tb) << 1), np.int32), full(m, np.int32),
+                             full(n, np.int32), full(k, np.int32), full(ra, np.int32),
+                             full(rb, np.int32), full(m, np.int32), full(al, np.float32),
+                             full(be, np.float32), z * sa, na + z * sb, na + nb + z * sc,
+                             np.concatenate([A, B, C]), name="strided")
+
+
+@pytest.mark.parametrize("integer", [False, True])
 @pytest.mark.parametrize("lay,m,n,k,batch", [
     ("NN", 16, 16, 16, 300), ("TN", 17, 9, 31, 200), ("NT", 80, 48, 33, 64),
     ("TT", 5, 80, 64, 100), ("NN", 3, 2, 7, 70000), ("NN", 81, 90, 40, 3)])
-def test_strided_equals_per_call(ctx, lay, m, n, k, batch):
+def test_strided_equals_per_call(ctx, lay, m, n, k, batch, integer):
+    """Every problem of the batch: bitwise equal to its own iaat_gemm call,
+    and against the FP64 oracle bit-exact (integer inputs) or within
+    1e-6 * K normwise (U[-1,1])."""
     ta, tb, ra, ca, rb, cb = stored(lay, m, n, k)
     rng = np.random.Generator(np.random.PCG64(inputs.SEED_BASE + 71 + m + n + k))
     pad = 3  # strides larger than the matrices
     sa, sb, sc = ra * ca + pad, rb * cb + pad, m * n + pad
-    A = rng.uniform(-1, 1, sa * batch).astype(np.float32)
-    B = rng.uniform(-1, 1, sb * batch).astype(np.float32)
-    C = rng.uniform(-1, 1, sc * batch).astype(np.float32)
+    draw = (lambda c: rng.integers(-4, 5, c).astype(np.float32)) if integer else \
+        (lambda c: rng.uniform(-1, 1, c).astype(np.float32))
+    A, B, C = draw(sa * batch), draw(sb * batch), draw(sc * batch)
     dA, dB = torch.from_numpy(A).to(DEV), torch.from_numpy(B).to(DEV)
     dC1, dC2 = torch.from_numpy(C).to(DEV), torch.from_numpy(C).to(DEV)
     s = torch.cuda.current_stream(DEV).cuda_stream
-    al, be = 1.25, -0.75
+    al, be = (1.5, -0.5) if integer else (1.25, -0.75)
     iaat.iaat_gemm_strided_batched(ctx, int(ta), int(tb), m, n, k, al, dA.data_ptr(), ra, sa,
                                    dB.data_ptr(), rb, sb, be, dC1.data_ptr(), m, sc, batch, s)
-    for z in ([0, 1, batch // 2, batch - 1] if batch > 1000 else range(batch)):
-        iaat.iaat_gemm(ctx, int(ta), int(tb), m, n, k, al, dA.data_ptr() + 4 * z * sa, ra,
-                       dB.data_ptr() + 4 * z * sb, rb, be, dC2.data_ptr() + 4 * z * sc, m, s)
+    L = iaat.lib()
+    pa, pb, pc = dA.data_ptr(), dB.data_ptr(), dC2.data_ptr()
+    for z in range(batch):
+        L.iaat_gemm(ctx, int(ta), int(tb), m, n, k, al, pa + 4 * z * sa, ra, pb + 4 * z * sb, rb,
+                    be, pc + 4 * z * sc, m, s)
     torch.cuda.synchronize(DEV)
     c1, c2 = dC1.cpu().numpy(), dC2.cpu().numpy()
-    zs = [0, 1, batch // 2, batch - 1] if batch > 1000 else range(batch)
-    for z in zs:
-        g1 = c1[z * sc:z * sc + m * n]
-        assert np.array_equal(g1.view(np.uint32), c2[z * sc:z * sc + m * n].view(np.uint32)), z
-        ref = oracle.gemm(int(ta), int(tb), m, n, k, al, A[z * sa:z * sa + ra * ca], ra,
-                          B[z * sb:z * sb + rb * cb], rb, be, C[z * sc:z * sc + m * n], m)
-        assert normwise(g1.reshape(n, m).T, ref) <= 1e-6 * k
+    assert np.array_equal(c1.view(np.uint32), c2.view(np.uint32))
+    ps = strided_set(ta, tb, m, n, k, ra, rb, sa, sb, sc, batch, al, be, A, B, C)
+    ref, _, off = oracle.gemm_batch(ps, nthreads=16)
+    got = c1.reshape(batch, sc)[:, :m * n].astype(np.float64)
+    want = ref[:batch * m * n].reshape(batch, m * n)
+    if integer:
+        assert np.array_equal(got, want)
+    else:
+        err = np.linalg.norm(got - want, axis=1) / np.linalg.norm(want, axis=1)
+        assert err.max() <= 1e-6 * k, float(err.max())
     # padding between problems untouched
-    for z in range(min(batch, 50)):
-        assert np.array_equal(c1[z * sc + m * n:(z + 1) * sc], C[z * sc + m * n:(z + 1) * sc])
+    pads = c1.reshape(batch, sc)[:, m * n:]
+    assert np.array_equal(pads, C.reshape(batch, sc)[:, m * n:])
 
 
 def test_strided_quick_return_and_errors(ctx):
