@@ -239,7 +239,7 @@ typedef struct iaat_problem {
  * the others are computed. */
 
 /* Computes every problem of a batch in one batched launch on `stream` (a
- * staging kernel whose work-groups each take windows of 4 problems, plus a
+ * staging kernel whose work-groups each take windows of up to 16 problems, plus a
  * companion kernel for problems too large to stage).  The descriptors are
  * already in device memory (`probs_dev`, count entries); validation,
  * tile-plan lookup and batching all run on the device, so the host does

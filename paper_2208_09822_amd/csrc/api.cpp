@@ -102,7 +102,8 @@ hipError_t launch_batch(iaat_ctx_t ctx, const iaat_problem* probs_dev, int64_t c
     const int64_t cap = 8LL * ctx->num_cu, need = (count + 3) / 4;
     return launch_vbatched_lowp(a, prec, (int)(need < cap ? need : cap), s);
   }
-  // work-groups take 4-problem windows
+  // at most one work-group per 4 problems; each takes windows of up to 16
+  // problems (a first one fixed by its index, then claimed from the counter)
   const int64_t units = (count + 3) / 4;
   const int grid = (int)(units < ctx->vb_grid ? units : ctx->vb_grid);
   return launch_vbatched_f32(a, grid, s);

@@ -84,7 +84,7 @@ __global__ __launch_bounds__(256) void copy_spans_kernel(const CopySpan* spans, 
 }
 
 // Device scratch of the allocation-free batched entry point: word 0 is the
-// window counter that hands 4-problem windows out to work-groups.  Each GPU
+// window counter that hands windows of up to 16 problems out to work-groups.  Each GPU
 // the library runs on holds its own copy until the process ends.  In host
 // code the name is only a stand-in: the device address comes from
 // scratch_address(), taken once per device.
