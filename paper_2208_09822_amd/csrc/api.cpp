@@ -92,6 +92,21 @@ static int max_plan_blocks(iaat_ctx_t ctx, int layout, int64_t m, int64_t n, int
   return maxb;
 }
 
+// Whether every block of the plans a problem uses (its super-blocks' edge
+// sizes) is a light family member.
+static bool plans_light(iaat_ctx_t ctx, int dt, int layout, int64_t m, int64_t n, int64_t nsm,
+                        int64_t nsn) {
+  const int lm = (int)(m - (nsm - 1) * kSuper), ln = (int)(n - (nsn - 1) * kSuper);
+  const int ms[2] = {kSuper, lm}, ns[2] = {kSuper, ln};
+  for (int a = (nsm > 1 ? 0 : 1); a < 2; ++a)
+    for (int b = (nsn > 1 ? 0 : 1); b < 2; ++b) {
+      const PlanEntry& e = ctx->table[plan_index(layout, ms[a], ns[b])];
+      for (uint32_t i = 0; i < e.nblk; ++i)
+        if (!kid_is_light(blk_kid(e.blk[i]), dt != IAAT_DT_F64)) return false;
+    }
+  return true;
+}
+
 // The batched launch(es) for one descriptor array: the staged FP32 kernel
 // and its companion, or the reduced-precision kernel.
 hipError_t launch_batch(iaat_ctx_t ctx, const iaat_problem* probs_dev, int64_t count, int prec,
@@ -298,7 +313,8 @@ static int x_strided(iaat_ctx_t ctx, int dt, const char* name, int ta, int tb, i
       return fail(IAAT_ERR_UNSUPPORTED, "%s: %lld x %lld is too large", name, (long long)m,
                   (long long)n);
     e = launch_xgemm(dt, P, layout, stride_a, stride_b, stride_c, batch, ctx->table_dev, (int)nsm,
-                     (int)nsn, max_plan_blocks(ctx, layout, m, n, nsm, nsn), s);
+                     (int)nsn, max_plan_blocks(ctx, layout, m, n, nsm, nsn),
+                     plans_light(ctx, dt, layout, m, n, nsm, nsn), s);
   }
   return e == hipSuccess ? IAAT_OK : hip_fail(e, name);
 }

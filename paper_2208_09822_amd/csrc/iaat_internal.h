@@ -36,6 +36,26 @@ static_assert(sizeof(PlanEntry) == 64, "plan entry must be 64 bytes");
 IAAT_HD uint32_t pack_block(int i0, int j0, int kid) {
   return (uint32_t)i0 | ((uint32_t)j0 << 8) | ((uint32_t)kid << 16);
 }
+// Family members with a small register footprint: for real FP64 at most two
+// matrix-core tiles, four strip rows or columns, four K-split outputs; for
+// complex types one tile, two strip rows or columns, two K-split outputs.
+// A kernel that holds only these keeps many wavefronts per SIMD; the FP64
+// and complex launches use it when every block of a plan is one of them.
+IAAT_HD constexpr bool kid_light(int fam, int p1, int p2, bool cplx) {
+  return cplx ? (fam == 0 ? p1 * p2 <= 1 : fam == 1 ? p1 <= 2 : fam == 2 ? p2 <= 2 : p1 * p2 <= 2)
+              : (fam == 0 ? p1 * p2 <= 2 : fam == 1 ? p1 <= 4 : fam == 2 ? p2 <= 4 : p1 * p2 <= 4);
+}
+IAAT_HD bool kid_is_light(int kid, bool cplx) {
+  switch (kid) {
+#define IAAT_LIGHT_CASE(id, fam, p1, p2, br, bc) \
+  case id:                                     \
+    return kid_light(fam, p1, p2, cplx);
+    IAAT_FOR_EACH_KID(IAAT_LIGHT_CASE)
+#undef IAAT_LIGHT_CASE
+    default:
+      return false;
+  }
+}
 IAAT_HD int blk_i0(uint32_t b) { return (int)(b & 0xffu); }
 IAAT_HD int blk_j0(uint32_t b) { return (int)((b >> 8) & 0xffu); }
 IAAT_HD int blk_kid(uint32_t b) { return (int)((b >> 16) & 0xffu); }

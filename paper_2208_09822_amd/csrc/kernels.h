@@ -75,9 +75,11 @@ struct XProb {
   int m, n, k, lda, ldb, ldc;
   double alpha_re, alpha_im, beta_re, beta_im;
 };
+// light: every block of the plans in use passes kid_is_light() (a kernel
+// compiled with only those members, at a smaller register budget).
 hipError_t launch_xgemm(int dt, const XProb& P, int layout, int64_t sa, int64_t sb, int64_t sc,
                         int64_t batch, const PlanEntry* table_dev, int nsm, int nsn, int max_blocks,
-                        hipStream_t s);
+                        bool light, hipStream_t s);
 hipError_t launch_xscale(int dt, const XProb& P, int64_t sc, int64_t batch, hipStream_t s);
 hipError_t launch_xgemm_vbatched(int dt, const iaat_xproblem* probs, int64_t count, int32_t* status,
                                  const PlanEntry* table_dev, hipStream_t s);

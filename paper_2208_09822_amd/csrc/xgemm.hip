@@ -27,6 +27,10 @@
 namespace iaat {
 namespace dev {
 
+#ifndef XWPE_LIGHT
+#define XWPE_LIGHT 6
+#endif
+
 typedef float xf4 __attribute__((ext_vector_type(4)));
 typedef double xd4 __attribute__((ext_vector_type(4)));
 
@@ -324,12 +328,14 @@ struct XBlock<2, DT, TA, TB, P1, P2> : XCols<DT, TA, TB, P2> {};
 template <int DT, int TA, int TB, int P1, int P2>
 struct XBlock<3, DT, TA, TB, P1, P2> : XKred<DT, TA, TB, P1, P2> {};
 
-template <int DT, int TA, int TB>
+// LIGHT: only the members kid_light() accepts are compiled in (the others
+// are never dispatched to such a kernel).
+template <int DT, int TA, int TB, bool LIGHT = false>
 __device__ __forceinline__ void xrun_block(int kid, const XProb& P, int i0, int j0) {
   switch (kid) {
-#define IAAT_XCASE(id, fam, p1, p2, br, bc)           \
-  case id:                                            \
-    XBlock<fam, DT, TA, TB, p1, p2>::run(P, i0, j0); \
+#define IAAT_XCASE(id, fam, p1, p2, br, bc)                                       \
+  case id:                                                                        \
+    if constexpr (!LIGHT || kid_light(fam, p1, p2, XT<DT>::CPLX)) XBlock<fam, DT, TA, TB, p1, p2>::run(P, i0, j0); \
     break;
     IAAT_FOR_EACH_KID(IAAT_XCASE)
 #undef IAAT_XCASE
@@ -354,9 +360,13 @@ __device__ __forceinline__ XProb xsub(const XProb& P, int sbi, int sbj) {
 }
 
 // One problem (or a same-size strided batch): grid.x = super-blocks,
-// grid.y = block slot in the plan, grid.z walks the batch.
-template <int DT, int TA, int TB>
-__global__ __launch_bounds__(64) void xgemm_kernel(XProb P, int64_t sa, int64_t sb, int64_t sc,
+// grid.y = block slot in the plan, grid.z walks the batch.  The register
+// budget is that of the largest member compiled in: LIGHT kernels run eight
+// wavefronts per SIMD, the full FP64 kernel four (a few spills cost less
+// than two wavefronts per SIMD), the full complex kernels what they need.
+template <int DT, int TA, int TB, bool LIGHT>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(LIGHT ? XWPE_LIGHT : XT<DT>::CPLX ? 1 : 4)))
+void xgemm_kernel(XProb P, int64_t sa, int64_t sb, int64_t sc,
                                                    int64_t batch, const PlanEntry* __restrict__ table,
                                                    int nsn) {
   const int sbk = blockIdx.x, b = blockIdx.y;
@@ -372,7 +382,7 @@ __global__ __launch_bounds__(64) void xgemm_kernel(XProb P, int64_t sa, int64_t 
     Q.A = (const char*)S0.A + es * z * sa;
     Q.B = (const char*)S0.B + es * z * sb;
     Q.C = (char*)S0.C + es * z * sc;
-    xrun_block<DT, TA, TB>(blk_kid(w), Q, blk_i0(w), blk_j0(w));
+    xrun_block<DT, TA, TB, LIGHT>(blk_kid(w), Q, blk_i0(w), blk_j0(w));
   }
 }
 
@@ -425,9 +435,10 @@ __device__ __forceinline__ const void* xunip(const void* p) {
 }
 
 // Uneven batch: wavefront q of the grid (grid-stride) takes problem q,
-// writes its status, and computes it (quick return: C = beta*C).
+// writes its status, and computes it (quick return: C = beta*C).  Every
+// member is compiled in; the budget is held to four wavefronts per SIMD.
 template <int DT>
-__global__ __launch_bounds__(64) void xgemm_vbatched_kernel(const iaat_xproblem* __restrict__ probs,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void xgemm_vbatched_kernel(const iaat_xproblem* __restrict__ probs,
                                                             int64_t count, int32_t* status,
                                                             const PlanEntry* __restrict__ table) {
   typedef typename XT<DT>::R R;
@@ -476,29 +487,39 @@ __global__ __launch_bounds__(64) void xgemm_vbatched_kernel(const iaat_xproblem*
 
 }  // namespace dev
 
+template <int DT, bool LIGHT>
+static void launch_x_kernel(const XProb& P, int layout, int64_t sa, int64_t sb, int64_t sc,
+                            int64_t batch, const PlanEntry* table_dev, int nsn, dim3 grid,
+                            hipStream_t s) {
+  const dim3 block(64);
+  switch (layout) {
+    case 0: hipLaunchKernelGGL((dev::xgemm_kernel<DT, 0, 0, LIGHT>), grid, block, 0, s, P, sa, sb, sc, batch, table_dev, nsn); break;
+    case 1: hipLaunchKernelGGL((dev::xgemm_kernel<DT, 1, 0, LIGHT>), grid, block, 0, s, P, sa, sb, sc, batch, table_dev, nsn); break;
+    case 2: hipLaunchKernelGGL((dev::xgemm_kernel<DT, 0, 1, LIGHT>), grid, block, 0, s, P, sa, sb, sc, batch, table_dev, nsn); break;
+    default: hipLaunchKernelGGL((dev::xgemm_kernel<DT, 1, 1, LIGHT>), grid, block, 0, s, P, sa, sb, sc, batch, table_dev, nsn); break;
+  }
+}
+
 template <int DT>
 static hipError_t launch_x_dt(const XProb& P, int layout, int64_t sa, int64_t sb, int64_t sc,
                               int64_t batch, const PlanEntry* table_dev, int nsm, int nsn,
-                              int max_blocks, hipStream_t s) {
+                              int max_blocks, bool light, hipStream_t s) {
   const dim3 grid((unsigned)(nsm * nsn), (unsigned)max_blocks,
-                  (unsigned)(batch < 65535 ? batch : 65535)),
-      block(64);
-  switch (layout) {
-    case 0: hipLaunchKernelGGL((dev::xgemm_kernel<DT, 0, 0>), grid, block, 0, s, P, sa, sb, sc, batch, table_dev, nsn); break;
-    case 1: hipLaunchKernelGGL((dev::xgemm_kernel<DT, 1, 0>), grid, block, 0, s, P, sa, sb, sc, batch, table_dev, nsn); break;
-    case 2: hipLaunchKernelGGL((dev::xgemm_kernel<DT, 0, 1>), grid, block, 0, s, P, sa, sb, sc, batch, table_dev, nsn); break;
-    default: hipLaunchKernelGGL((dev::xgemm_kernel<DT, 1, 1>), grid, block, 0, s, P, sa, sb, sc, batch, table_dev, nsn); break;
-  }
+                  (unsigned)(batch < 65535 ? batch : 65535));
+  if (light)
+    launch_x_kernel<DT, true>(P, layout, sa, sb, sc, batch, table_dev, nsn, grid, s);
+  else
+    launch_x_kernel<DT, false>(P, layout, sa, sb, sc, batch, table_dev, nsn, grid, s);
   return hipGetLastError();
 }
 
 hipError_t launch_xgemm(int dt, const XProb& P, int layout, int64_t sa, int64_t sb, int64_t sc,
                         int64_t batch, const PlanEntry* table_dev, int nsm, int nsn, int max_blocks,
-                        hipStream_t s) {
+                        bool light, hipStream_t s) {
   switch (dt) {
-    case IAAT_DT_F64: return launch_x_dt<IAAT_DT_F64>(P, layout, sa, sb, sc, batch, table_dev, nsm, nsn, max_blocks, s);
-    case IAAT_DT_C64: return launch_x_dt<IAAT_DT_C64>(P, layout, sa, sb, sc, batch, table_dev, nsm, nsn, max_blocks, s);
-    case IAAT_DT_C128: return launch_x_dt<IAAT_DT_C128>(P, layout, sa, sb, sc, batch, table_dev, nsm, nsn, max_blocks, s);
+    case IAAT_DT_F64: return launch_x_dt<IAAT_DT_F64>(P, layout, sa, sb, sc, batch, table_dev, nsm, nsn, max_blocks, light, s);
+    case IAAT_DT_C64: return launch_x_dt<IAAT_DT_C64>(P, layout, sa, sb, sc, batch, table_dev, nsm, nsn, max_blocks, light, s);
+    case IAAT_DT_C128: return launch_x_dt<IAAT_DT_C128>(P, layout, sa, sb, sc, batch, table_dev, nsm, nsn, max_blocks, light, s);
     default: return hipErrorInvalidValue;
   }
 }
