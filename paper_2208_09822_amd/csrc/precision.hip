@@ -321,9 +321,13 @@ __device__ void lowp_problem(const iaat_problem& P) {
 }
 
 // Wavefront w of the grid (four per work-group) takes problems w, w + W, ...
-// (W wavefronts in all): small problems keep every wavefront busy.
+// (W wavefronts in all): small problems keep every wavefront busy.  The FP8
+// kernel is held to eight wavefronts per SIMD (a few spills; its widening
+// of the codes adds latency that more wavefronts hide); for the others more
+// wavefronts per SIMD measured slower.
 template <int PREC>
-__global__ __launch_bounds__(256) void vbatched_lowp_kernel(VbArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC == IAAT_PREC_F8E4M3 ? 8 : 1)))
+void vbatched_lowp_kernel(VbArgs a) {
   const int64_t W = (int64_t)gridDim.x * 4;
   const int64_t w0 = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int l = (int)(threadIdx.x & 63);
