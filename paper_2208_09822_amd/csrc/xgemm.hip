@@ -27,9 +27,6 @@
 namespace iaat {
 namespace dev {
 
-#ifndef XWPE_LIGHT
-#define XWPE_LIGHT 6
-#endif
 
 typedef float xf4 __attribute__((ext_vector_type(4)));
 typedef double xd4 __attribute__((ext_vector_type(4)));
@@ -359,17 +356,19 @@ __device__ __forceinline__ XProb xsub(const XProb& P, int sbi, int sbj) {
   return S;
 }
 
-// One problem (or a same-size strided batch): grid.x = super-blocks,
-// grid.y = block slot in the plan, grid.z walks the batch.  The register
+// One problem (or a same-size strided batch): one plan block of one
+// super-block of one problem per work-group (the host launches very long
+// batches and very many super-blocks in pieces).  The register
 // budget is that of the largest member compiled in: LIGHT kernels run eight
-// wavefronts per SIMD, the full FP64 kernel four (a few spills cost less
-// than two wavefronts per SIMD), the full complex kernels what they need.
+// wavefronts per SIMD, full kernels four (complex FP64 with a few spills).
 template <int DT, int TA, int TB, bool LIGHT>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(LIGHT ? XWPE_LIGHT : XT<DT>::CPLX ? 1 : 4)))
-void xgemm_kernel(XProb P, int64_t sa, int64_t sb, int64_t sc,
-                                                   int64_t batch, const PlanEntry* __restrict__ table,
-                                                   int nsn) {
-  const int sbk = blockIdx.x, b = blockIdx.y;
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(LIGHT ? 8 : 4)))
+void xgemm_kernel(XProb P, int64_t sa, int64_t sb, int64_t sc, int64_t batch,
+                  const PlanEntry* __restrict__ table, int nsn, int sb0, int slots) {
+  // grid.x = problem * slots + block slot (a problem's blocks run side by
+  // side, sharing its operands in cache), grid.y = super-block - sb0
+  const int sbk = sb0 + (int)blockIdx.y, b = (int)(blockIdx.x % (unsigned)slots);
+  const int64_t z = blockIdx.x / (unsigned)slots;
   const int sbi = sbk / nsn, sbj = sbk - sbi * nsn;
   const int64_t es = XT<DT>::CPLX ? 2 * (int64_t)sizeof(typename XT<DT>::R)
                                   : (int64_t)sizeof(typename XT<DT>::R);
@@ -377,13 +376,14 @@ void xgemm_kernel(XProb P, int64_t sa, int64_t sb, int64_t sc,
   const PlanEntry* e = table + plan_index(TA | (TB << 1), S0.m, S0.n);
   if (b >= (int)e->nblk) return;
   const uint32_t w = e->blk[b];
-  for (int64_t z = blockIdx.z; z < batch; z += gridDim.z) {
-    XProb Q = S0;
-    Q.A = (const char*)S0.A + es * z * sa;
-    Q.B = (const char*)S0.B + es * z * sb;
-    Q.C = (char*)S0.C + es * z * sc;
-    xrun_block<DT, TA, TB, LIGHT>(blk_kid(w), Q, blk_i0(w), blk_j0(w));
-  }
+  // one block of one problem per work-group (no loop over the batch: a loop
+  // around the member switch more than doubled the registers it takes)
+  if (z >= batch) return;
+  XProb Q = S0;
+  Q.A = (const char*)S0.A + es * z * sa;
+  Q.B = (const char*)S0.B + es * z * sb;
+  Q.C = (char*)S0.C + es * z * sc;
+  xrun_block<DT, TA, TB, LIGHT>(blk_kid(w), Q, blk_i0(w), blk_j0(w));
 }
 
 // C = beta*C (alpha == 0 or K == 0), batch along grid.y.
@@ -407,9 +407,10 @@ __global__ __launch_bounds__(256) void xscale_kernel(XProb P, int64_t sc, int64_
 }
 
 // A whole problem on one wavefront: every super-block, every plan block.
-// Out of line per layout (the batched kernel calls one of four).
+// Inlined, so the kernel's register budget applies to it (an out-of-line
+// copy took 248 registers whatever the kernel asked for).
 template <int DT, int TA, int TB>
-__device__ __noinline__ void xsolve(XProb P, const PlanEntry* table) {
+__device__ __forceinline__ void xsolve(XProb P, const PlanEntry* table) {
   const int nsm = (P.m + kSuper - 1) / kSuper, nsn = (P.n + kSuper - 1) / kSuper;
   for (int sbj = 0; sbj < nsn; ++sbj)
     for (int sbi = 0; sbi < nsm; ++sbi) {
@@ -436,9 +437,11 @@ __device__ __forceinline__ const void* xunip(const void* p) {
 
 // Uneven batch: wavefront q of the grid (grid-stride) takes problem q,
 // writes its status, and computes it (quick return: C = beta*C).  Every
-// member is compiled in; the budget is held to four wavefronts per SIMD.
+// member is compiled in; the budget is held to five wavefronts per SIMD
+// for complex FP32 (no spills) and four for the others.
 template <int DT>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void xgemm_vbatched_kernel(const iaat_xproblem* __restrict__ probs,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(DT == IAAT_DT_C64 ? 5 : 4)))
+void xgemm_vbatched_kernel(const iaat_xproblem* __restrict__ probs,
                                                             int64_t count, int32_t* status,
                                                             const PlanEntry* __restrict__ table) {
   typedef typename XT<DT>::R R;
@@ -489,14 +492,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void xg
 
 template <int DT, bool LIGHT>
 static void launch_x_kernel(const XProb& P, int layout, int64_t sa, int64_t sb, int64_t sc,
-                            int64_t batch, const PlanEntry* table_dev, int nsn, dim3 grid,
-                            hipStream_t s) {
+                            int64_t batch, const PlanEntry* table_dev, int nsn, int sb0, int slots,
+                            dim3 grid, hipStream_t s) {
   const dim3 block(64);
   switch (layout) {
-    case 0: hipLaunchKernelGGL((dev::xgemm_kernel<DT, 0, 0, LIGHT>), grid, block, 0, s, P, sa, sb, sc, batch, table_dev, nsn); break;
-    case 1: hipLaunchKernelGGL((dev::xgemm_kernel<DT, 1, 0, LIGHT>), grid, block, 0, s, P, sa, sb, sc, batch, table_dev, nsn); break;
-    case 2: hipLaunchKernelGGL((dev::xgemm_kernel<DT, 0, 1, LIGHT>), grid, block, 0, s, P, sa, sb, sc, batch, table_dev, nsn); break;
-    default: hipLaunchKernelGGL((dev::xgemm_kernel<DT, 1, 1, LIGHT>), grid, block, 0, s, P, sa, sb, sc, batch, table_dev, nsn); break;
+    case 0: hipLaunchKernelGGL((dev::xgemm_kernel<DT, 0, 0, LIGHT>), grid, block, 0, s, P, sa, sb, sc, batch, table_dev, nsn, sb0, slots); break;
+    case 1: hipLaunchKernelGGL((dev::xgemm_kernel<DT, 1, 0, LIGHT>), grid, block, 0, s, P, sa, sb, sc, batch, table_dev, nsn, sb0, slots); break;
+    case 2: hipLaunchKernelGGL((dev::xgemm_kernel<DT, 0, 1, LIGHT>), grid, block, 0, s, P, sa, sb, sc, batch, table_dev, nsn, sb0, slots); break;
+    default: hipLaunchKernelGGL((dev::xgemm_kernel<DT, 1, 1, LIGHT>), grid, block, 0, s, P, sa, sb, sc, batch, table_dev, nsn, sb0, slots); break;
   }
 }
 
@@ -504,13 +507,29 @@ template <int DT>
 static hipError_t launch_x_dt(const XProb& P, int layout, int64_t sa, int64_t sb, int64_t sc,
                               int64_t batch, const PlanEntry* table_dev, int nsm, int nsn,
                               int max_blocks, bool light, hipStream_t s) {
-  const dim3 grid((unsigned)(nsm * nsn), (unsigned)max_blocks,
-                  (unsigned)(batch < 65535 ? batch : 65535));
-  if (light)
-    launch_x_kernel<DT, true>(P, layout, sa, sb, sc, batch, table_dev, nsn, grid, s);
-  else
-    launch_x_kernel<DT, false>(P, layout, sa, sb, sc, batch, table_dev, nsn, grid, s);
-  return hipGetLastError();
+  const int64_t es = dev::XT<DT>::CPLX ? 2 * (int64_t)sizeof(typename dev::XT<DT>::R)
+                                       : (int64_t)sizeof(typename dev::XT<DT>::R);
+  if (max_blocks < 1) return hipSuccess;
+  const int64_t nsb = (int64_t)nsm * nsn;
+  const int64_t zmax = 0x7fffffffLL / max_blocks;  // grid.x limit
+  for (int64_t z0 = 0; z0 < batch; z0 += zmax) {
+    const int64_t nz = batch - z0 < zmax ? batch - z0 : zmax;
+    XProb Q = P;
+    Q.A = (const char*)P.A + es * z0 * sa;
+    Q.B = (const char*)P.B + es * z0 * sb;
+    Q.C = (char*)P.C + es * z0 * sc;
+    for (int64_t s0 = 0; s0 < nsb; s0 += 65535) {  // grid.y limit
+      const int64_t ns = nsb - s0 < 65535 ? nsb - s0 : 65535;
+      const dim3 grid((unsigned)(nz * max_blocks), (unsigned)ns, 1);
+      if (light)
+        launch_x_kernel<DT, true>(Q, layout, sa, sb, sc, nz, table_dev, nsn, (int)s0, max_blocks, grid, s);
+      else
+        launch_x_kernel<DT, false>(Q, layout, sa, sb, sc, nz, table_dev, nsn, (int)s0, max_blocks, grid, s);
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_xgemm(int dt, const XProb& P, int layout, int64_t sa, int64_t sb, int64_t sc,

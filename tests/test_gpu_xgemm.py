@@ -288,3 +288,37 @@ def test_uneven_batch_status_codes(ctx):
     with pytest.raises(iaat.IaatError) as e:
         iaat.iaat_xgemm_vbatched(ctx, iaat.IAAT_DT_F64, 0, 8)
     assert e.value.code == -2
+
+
+@pytest.mark.parametrize("dt", ["D", "C", "Z"])
+def test_strided_batch_longer_than_one_grid_dimension(ctx, dt):
+    """65,600 problems in one strided call, on a plan of small members (1 x 1)
+    and on one that needs the full family (3 x 3, a 3 x 3 K-split block):
+    problems on both sides of index 65,535 against the oracle, bit for bit
+    (integer inputs)."""
+    np_t = DTYPES[dt][1]
+    batch, k = 65600, 5
+    fns = {"D": iaat.iaat_dgemm_strided_batched, "C": iaat.iaat_cgemm_strided_batched,
+           "Z": iaat.iaat_zgemm_strided_batched}
+    s = torch.cuda.current_stream(DEV).cuda_stream
+    for (m, n) in ((1, 1), (3, 3)):
+        print("[strided-long] dt=%s m=%d n=%d batch=%d" % (dt, m, n, batch), flush=True)
+        rng = np.random.Generator(np.random.PCG64(900 + m))
+        A = draw(rng, dt, m * k * batch, True)
+        B = draw(rng, dt, k * n * batch, True)
+        C = draw(rng, dt, m * n * batch, True)
+        al, be = scalars(dt, True)
+        dA, dB, dC = (torch.from_numpy(x).to(DEV) for x in (A, B, C))
+        if dt == "D":
+            al, be = al.real, be.real
+        fns[dt](ctx, 0, 0, m, n, k, al, dA.data_ptr(), m, m * k, dB.data_ptr(), k, k * n, be,
+                dC.data_ptr(), m, m * n, batch, s)
+        torch.cuda.synchronize(DEV)
+        got = dC.cpu().numpy()
+        for z in sorted({0, 1, 4999, 65533, 65534, 65535, 65536, 65537, batch - 1}):
+            a0 = np.ascontiguousarray(A[z * m * k:(z + 1) * m * k])
+            b0 = np.ascontiguousarray(B[z * k * n:(z + 1) * k * n])
+            c0 = np.ascontiguousarray(C[z * m * n:(z + 1) * m * n])
+            ref = oracle_call(dt, 0, 0, m, n, k, complex(al), a0, m, b0, k, complex(be), c0, m)
+            want = np.asarray(ref).T.reshape(-1)  # column-major, ldc = m
+            assert np.array_equal(got[z * m * n:(z + 1) * m * n], want.astype(np_t)), (dt, m, n, z)
