@@ -37,32 +37,35 @@ __global__ __launch_bounds__(64) void scale_kernel(float* C, int m, int n, int l
   scale_columns(C, m, n, ldc, beta, (int)blockIdx.x, (int)gridDim.x);
 }
 
-// Same-size batch: problem z has operands at A + z*sa, B + z*sb, C + z*sc;
-// grid.z walks the problems (grid-stride), grid.x/y as in gemm_f32_kernel,
-// with the one plan every problem shares.
+// Same-size batch: problem z has operands at A + z*sa, B + z*sb, C + z*sc,
+// with the one plan every problem shares.  One plan block of one
+// super-block of one problem per work-group: grid.x = problem * slots +
+// block slot (a problem's blocks side by side), grid.y = super-block - sb0;
+// the host launches very long batches in pieces.  There is no loop over the
+// batch: a loop around the block switch raises the registers it takes.
 template <int TA, int TB>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4))) void gemm_f32_strided_kernel(
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void gemm_f32_strided_kernel(
     Prob P, int64_t sa, int64_t sb, int64_t sc, int64_t batch, const PlanEntry* __restrict__ table,
-    int nsn) {
-  const int sbk = blockIdx.x, b = blockIdx.y;
+    int nsn, int sb0, int slots) {
+  const int sbk = sb0 + (int)blockIdx.y, b = (int)(blockIdx.x % (unsigned)slots);
+  const int64_t z = blockIdx.x / (unsigned)slots;
+  if (z >= batch) return;
   const int sbi = sbk / nsn, sbj = sbk - sbi * nsn;
   const bool nar = narrow(P);
   const PlanEntry* e = table + plan_index(TA | (TB << 1), sub_problem<TA, TB>(P, sbi, sbj).m,
                                           sub_problem<TA, TB>(P, sbi, sbj).n);
   if (nar ? b >= (int)e->nblk : b > 0) return;
-  for (int64_t z = blockIdx.z; z < batch; z += gridDim.z) {
-    Prob Q = P;
-    Q.A += z * sa;
-    Q.B += z * sb;
-    Q.C += z * sc;
-    const Prob S = sub_problem<TA, TB>(Q, sbi, sbj);
-    if (!nar) {
-      wide_subproblem<TA, TB>(S);
-      continue;
-    }
-    const uint32_t w = e->blk[b];
-    run_block<TA, TB>(blk_kid(w), S, blk_i0(w), blk_j0(w));
+  Prob Q = P;
+  Q.A += z * sa;
+  Q.B += z * sb;
+  Q.C += z * sc;
+  const Prob S = sub_problem<TA, TB>(Q, sbi, sbj);
+  if (!nar) {
+    wide_subproblem<TA, TB>(S);
+    return;
   }
+  const uint32_t w = e->blk[b];
+  run_block<TA, TB>(blk_kid(w), S, blk_i0(w), blk_j0(w));
 }
 
 __global__ __launch_bounds__(64) void scale_strided_kernel(float* C, int m, int n, int ldc, float beta,
@@ -138,15 +141,31 @@ hipError_t launch_gemm_f32(const dev::Prob& P, int layout, const PlanEntry* tabl
 hipError_t launch_gemm_f32_strided(const dev::Prob& P, int layout, const PlanEntry* table_dev, int nsm,
                                    int nsn, int max_blocks, int64_t sa, int64_t sb, int64_t sc,
                                    int64_t batch, hipStream_t stream) {
-  const unsigned gz = (unsigned)(batch < 65535 ? batch : 65535);
-  const dim3 grid((unsigned)(nsm * nsn), (unsigned)max_blocks, gz), block(64);
-  switch (layout) {
-    case 0: hipLaunchKernelGGL((dev::gemm_f32_strided_kernel<0, 0>), grid, block, 0, stream, P, sa, sb, sc, batch, table_dev, nsn); break;
-    case 1: hipLaunchKernelGGL((dev::gemm_f32_strided_kernel<1, 0>), grid, block, 0, stream, P, sa, sb, sc, batch, table_dev, nsn); break;
-    case 2: hipLaunchKernelGGL((dev::gemm_f32_strided_kernel<0, 1>), grid, block, 0, stream, P, sa, sb, sc, batch, table_dev, nsn); break;
-    default: hipLaunchKernelGGL((dev::gemm_f32_strided_kernel<1, 1>), grid, block, 0, stream, P, sa, sb, sc, batch, table_dev, nsn); break;
+  if (max_blocks < 1) return hipSuccess;
+  const dim3 block(64);
+  const int64_t nsb = (int64_t)nsm * nsn;
+  const int64_t zmax = 0x7fffffffLL / max_blocks;  // grid.x limit
+  for (int64_t z0 = 0; z0 < batch; z0 += zmax) {
+    const int64_t nz = batch - z0 < zmax ? batch - z0 : zmax;
+    dev::Prob Q = P;
+    Q.A += z0 * sa;
+    Q.B += z0 * sb;
+    Q.C += z0 * sc;
+    for (int64_t s0 = 0; s0 < nsb; s0 += 65535) {  // grid.y limit
+      const int64_t ns = nsb - s0 < 65535 ? nsb - s0 : 65535;
+      const dim3 grid((unsigned)(nz * max_blocks), (unsigned)ns, 1);
+      const int b0 = (int)s0;
+      switch (layout) {
+        case 0: hipLaunchKernelGGL((dev::gemm_f32_strided_kernel<0, 0>), grid, block, 0, stream, Q, sa, sb, sc, nz, table_dev, nsn, b0, max_blocks); break;
+        case 1: hipLaunchKernelGGL((dev::gemm_f32_strided_kernel<1, 0>), grid, block, 0, stream, Q, sa, sb, sc, nz, table_dev, nsn, b0, max_blocks); break;
+        case 2: hipLaunchKernelGGL((dev::gemm_f32_strided_kernel<0, 1>), grid, block, 0, stream, Q, sa, sb, sc, nz, table_dev, nsn, b0, max_blocks); break;
+        default: hipLaunchKernelGGL((dev::gemm_f32_strided_kernel<1, 1>), grid, block, 0, stream, Q, sa, sb, sc, nz, table_dev, nsn, b0, max_blocks); break;
+      }
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
   }
-  return hipGetLastError();
+  return hipSuccess;
 }
 
 hipError_t launch_scale_f32_strided(float* C, int m, int n, int ldc, float beta, int64_t sc,
