@@ -437,10 +437,11 @@ __device__ __forceinline__ const void* xunip(const void* p) {
 
 // Uneven batch: wavefront q of the grid (grid-stride) takes problem q,
 // writes its status, and computes it (quick return: C = beta*C).  Every
-// member is compiled in; the budget is held to five wavefronts per SIMD
-// for complex FP32 (no spills) and four for the others.
+// member is compiled in; the register budget (no spills) allows five
+// wavefronts per SIMD for complex FP32, four for FP64 and three for complex
+// FP64 (four, with spills, measured slower).
 template <int DT>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(DT == IAAT_DT_C64 ? 5 : 4)))
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(DT == IAAT_DT_C64 ? 5 : DT == IAAT_DT_C128 ? 3 : 4)))
 void xgemm_vbatched_kernel(const iaat_xproblem* __restrict__ probs,
                                                             int64_t count, int32_t* status,
                                                             const PlanEntry* __restrict__ table) {
