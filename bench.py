@@ -39,14 +39,24 @@ KERNEL = "vbatched_f32_kernel"
 
 
 def source_hash() -> str:
-    """Hash of the device sources: a stored counter profile applies only to
-    the kernel it was taken on."""
-    h = hashlib.sha256()
+    """Hash of the sources the batched FP32 kernel is compiled from (its
+    file and every local header it includes, transitively): a stored counter
+    profile applies only to the kernel it was taken on."""
+    import re
     csrc = os.path.join(ROOT, "paper_2208_09822_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".h")):
-            h.update(name.encode())
-            h.update(open(os.path.join(csrc, name), "rb").read())
+    todo, seen = [os.path.join(csrc, "batched.hip")], set()
+    while todo:
+        path = os.path.normpath(todo.pop())
+        if path in seen or not os.path.exists(path):
+            continue
+        seen.add(path)
+        text = open(path, "rb").read()
+        for inc in re.findall(rb'#include "([^"]+)"', text):
+            todo.append(os.path.join(os.path.dirname(path), inc.decode()))
+    h = hashlib.sha256()
+    for path in sorted(seen):
+        h.update(os.path.relpath(path, ROOT).encode())
+        h.update(open(path, "rb").read())
     return h.hexdigest()[:16]
 
 
