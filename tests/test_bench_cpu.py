@@ -24,3 +24,26 @@ def test_counter_profile_is_consistent():
     assert abs(hbm - d["hbm_bytes_per_launch"]) <= 1e-3 * hbm
     assert abs(cal["fetch_size_kib"] * 1024 * cal["fetch_scale"] - cal["bytes"]) <= 1e-3 * cal["bytes"]
     assert 0.9 < d["traffic_over_algorithmic"] < 1.5
+
+
+def test_traffic_hash_follows_the_kernel_sources(tmp_path, monkeypatch):
+    """The stored traffic applies while the batched kernel's file and its
+    local headers are unchanged: the hash covers exactly that include
+    closure (a change to another device source leaves it alone)."""
+    sys.path.insert(0, ROOT)
+    import bench
+    h0 = bench.source_hash()
+    # a copy of the tree's device sources; edit one file at a time
+    import shutil
+    src = os.path.join(ROOT, "paper_2208_09822_amd", "csrc")
+    fake = tmp_path / "paper_2208_09822_amd" / "csrc"
+    shutil.copytree(src, fake, ignore=shutil.ignore_patterns("*.o"))
+    shutil.copytree(os.path.join(ROOT, "include"), tmp_path / "include")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.source_hash() == h0
+    with open(fake / "xgemm.hip", "a") as f:  # not included by the batched kernel
+        f.write("\n// edit\n")
+    assert bench.source_hash() == h0
+    with open(fake / "tiles.h", "a") as f:  # included (through batched.hip)
+        f.write("\n// edit\n")
+    assert bench.source_hash() != h0
