@@ -119,12 +119,18 @@ int iaat_gemm(iaat_ctx_t ctx, int ta, int tb, int64_t m, int64_t n, int64_t k,
 /* Same-size repeated problems (the case the closing remark of Section VI
  * names as IAAT's best fit): `batch` problems of one shape and layout,
  * problem z at A + z*stride_a, B + z*stride_b, C + z*stride_c (strides in
- * elements).  One launch; the tile plan is looked up once and shared.
+ * elements).  The tile plan is looked up once and shared: one launch of
+ * the strided kernel; or, when both sides of C are 40..80 and not both
+ * multiples of 32 and the operands fit the staging buffer (where the staged
+ * batched kernel of iaat_gemm_vbatched is faster), a descriptor-writing
+ * launch and the staged kernel, with a stream-ordered descriptor buffer of
+ * 64 bytes per problem (hipMallocAsync / hipFreeAsync on `stream`).
  * Argument numbers: ta 2, tb 3, m 4, n 5, k 6, A 8, lda 9, stride_a 10,
  * B 11, ldb 12, stride_b 13, C 15, ldc 16, stride_c 17, batch 18.  Strides
  * are >= 0; when batch > 1, stride_c >= ldc*n (outputs must not overlap).
- * Quick returns and NULL rules as iaat_gemm.  Does not allocate.  Results
- * are bitwise those of iaat_gemm on each problem. */
+ * Quick returns and NULL rules as iaat_gemm.  Allocates only that
+ * descriptor buffer.  Results are bitwise those of iaat_gemm on each
+ * problem. */
 int iaat_gemm_strided_batched(iaat_ctx_t ctx, int ta, int tb, int64_t m, int64_t n, int64_t k,
                               float alpha, const float* A, int64_t lda, int64_t stride_a,
                               const float* B, int64_t ldb, int64_t stride_b, float beta, float* C,

@@ -235,6 +235,22 @@ int iaat_gemm(iaat_ctx_t ctx, int ta, int tb, int64_t m, int64_t n, int64_t k, f
   return e == hipSuccess ? IAAT_OK : hip_fail(e, "iaat_gemm: launch");
 }
 
+// Same-size batches the staged batched kernel runs faster than the strided
+// kernel (measured on MI355X: 1.2-2x on 40^3, 56^3, 72^3, 80^3, 80x80x16,
+// 48x48x16): both sides of C at least 40 and not both multiples of 32, and
+// every operand span fits the staging buffer.  Shapes with both sides
+// multiples of 32, or one side of 16 or less, stay on the strided kernel,
+// whose one-block-per-work-group grid suits them better.
+static bool strided_to_staged(int ta, int tb, int64_t m, int64_t n, int64_t k, int64_t lda,
+                              int64_t ldb, int64_t ldc) {
+  if (m < 40 || n < 40 || m > kSuper || n > kSuper || k > kSuper) return false;
+  if (m % 32 == 0 && n % 32 == 0) return false;
+  const int64_t sa = ta ? lda * (m - 1) + k : lda * (k - 1) + m;
+  const int64_t sb = tb ? ldb * (k - 1) + n : ldb * (n - 1) + k;
+  const int64_t sc = ldc * (n - 1) + m;
+  return sa + sb + sc <= 19200;  // the largest small-domain problem, 80 x 80 x 80
+}
+
 int iaat_gemm_strided_batched(iaat_ctx_t ctx, int ta, int tb, int64_t m, int64_t n, int64_t k,
                               float alpha, const float* A, int64_t lda, int64_t stride_a,
                               const float* B, int64_t ldb, int64_t stride_b, float beta, float* C,
@@ -269,6 +285,20 @@ int iaat_gemm_strided_batched(iaat_ctx_t ctx, int ta, int tb, int64_t m, int64_t
     return fail(IAAT_ERR_UNSUPPORTED, "iaat_gemm_strided_batched: %lld x %lld is too large",
                 (long long)m, (long long)n);
   dev::Prob P{A, B, C, (int)m, (int)n, (int)k, (int)lda, (int)ldb, (int)ldc, alpha, beta};
+  if (strided_to_staged(ta, tb, m, n, k, lda, ldb, ldc)) {
+    // the staged batched kernel, on descriptors written on the device (the
+    // same blocks in the same order: bitwise the same C)
+    iaat_problem* d = nullptr;
+    e = hipMallocAsync((void**)&d, (size_t)batch * sizeof(iaat_problem), s);
+    if (e == hipSuccess) {
+      e = launch_strided_desc(d, batch, P, layout, stride_a, stride_b, stride_c, s);
+      if (e == hipSuccess) e = launch_batch(ctx, d, batch, IAAT_PREC_F32, nullptr, s);
+      const hipError_t ef = hipFreeAsync(d, s);
+      if (e == hipSuccess) e = ef;
+      return e == hipSuccess ? IAAT_OK : hip_fail(e, "iaat_gemm_strided_batched: staged launch");
+    }
+    (void)hipGetLastError();  // no stream-ordered memory: the strided kernel below
+  }
   e = launch_gemm_f32_strided(P, layout, ctx->table_dev, (int)nsm, (int)nsn,
                               max_plan_blocks(ctx, layout, m, n, nsm, nsn), stride_a, stride_b,
                               stride_c, batch, s);

@@ -35,6 +35,9 @@ hipError_t launch_scale_f32(float* C, int m, int n, int ldc, float beta, hipStre
 hipError_t launch_gemm_f32_strided(const dev::Prob& P, int layout, const PlanEntry* table_dev, int nsm,
                                    int nsn, int max_blocks, int64_t sa, int64_t sb, int64_t sc,
                                    int64_t batch, hipStream_t stream);
+// Descriptors (one iaat_problem per problem) of a same-size strided batch.
+hipError_t launch_strided_desc(iaat_problem* d, int64_t batch, const dev::Prob& P, int layout,
+                               int64_t sa, int64_t sb, int64_t sc, hipStream_t stream);
 hipError_t launch_scale_f32_strided(float* C, int m, int n, int ldc, float beta, int64_t sc,
                                     int64_t batch, hipStream_t stream);
 // The batched FP32 launch: a kernel clearing the ticket counter (when there

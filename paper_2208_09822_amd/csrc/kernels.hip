@@ -68,6 +68,30 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void ge
   run_block<TA, TB>(blk_kid(w), S, blk_i0(w), blk_j0(w));
 }
 
+// Descriptors of a same-size strided batch (problem z at A + z*sa, ...), for
+// the staged batched kernel.
+__global__ __launch_bounds__(256) void strided_desc_kernel(iaat_problem* d, int64_t batch, Prob P,
+                                                           int trans, int64_t sa, int64_t sb,
+                                                           int64_t sc) {
+  for (int64_t z = (int64_t)blockIdx.x * 256 + threadIdx.x; z < batch; z += (int64_t)gridDim.x * 256) {
+    iaat_problem q;
+    q.A = P.A + z * sa;
+    q.B = P.B + z * sb;
+    q.C = P.C + z * sc;
+    q.trans = trans;
+    q.m = P.m;
+    q.n = P.n;
+    q.k = P.k;
+    q.lda = P.lda;
+    q.ldb = P.ldb;
+    q.ldc = P.ldc;
+    q.alpha = P.alpha;
+    q.beta = P.beta;
+    q.ab_scale = 1.0f;
+    d[z] = q;
+  }
+}
+
 __global__ __launch_bounds__(64) void scale_strided_kernel(float* C, int m, int n, int ldc, float beta,
                                                            int64_t sc, int64_t batch) {
   for (int64_t z = blockIdx.y; z < batch; z += gridDim.y)
@@ -166,6 +190,14 @@ hipError_t launch_gemm_f32_strided(const dev::Prob& P, int layout, const PlanEnt
     }
   }
   return hipSuccess;
+}
+
+hipError_t launch_strided_desc(iaat_problem* d, int64_t batch, const dev::Prob& P, int layout,
+                               int64_t sa, int64_t sb, int64_t sc, hipStream_t stream) {
+  const int64_t g = (batch + 255) / 256;
+  hipLaunchKernelGGL(dev::strided_desc_kernel, dim3((unsigned)(g < 4096 ? g : 4096)), dim3(256), 0, stream, d,
+                     batch, P, layout, sa, sb, sc);
+  return hipGetLastError();
 }
 
 hipError_t launch_scale_f32_strided(float* C, int m, int n, int ldc, float beta, int64_t sc,

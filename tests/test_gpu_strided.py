@@ -44,7 +44,9 @@ def strided_set(ta, tb, m, n, k, ra, rb, sa, sb, sc, batch, al, be, A, B, C):
 @pytest.mark.parametrize("integer", [False, True])
 @pytest.mark.parametrize("lay,m,n,k,batch", [
     ("NN", 16, 16, 16, 300), ("TN", 17, 9, 31, 200), ("NT", 80, 48, 33, 64),
-    ("TT", 5, 80, 64, 100), ("NN", 3, 2, 7, 70000), ("NN", 81, 90, 40, 3)])
+    ("TT", 5, 80, 64, 100), ("NN", 3, 2, 7, 70000), ("NN", 81, 90, 40, 3),
+    # shapes the library routes to the staged batched kernel
+    ("TN", 56, 72, 40, 500), ("TT", 40, 80, 80, 64), ("NN", 80, 80, 80, 100)])
 def test_strided_equals_per_call(ctx, lay, m, n, k, batch, integer):
     """Every problem of the batch: bitwise equal to its own iaat_gemm call,
     and against the FP64 oracle bit-exact (integer inputs) or within
