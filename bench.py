@@ -437,7 +437,7 @@ def main() -> int:
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU only (no multi-GPU path); "
+        print("bench.py: the benchmark measures one GPU only (no multi-GPU path); "
               "run with --gpus 1", file=sys.stderr)
         return 2
 

@@ -236,9 +236,9 @@ int iaat_gemm(iaat_ctx_t ctx, int ta, int tb, int64_t m, int64_t n, int64_t k, f
 }
 
 // Same-size batches the staged batched kernel runs faster than the strided
-// kernel (measured on MI355X: 1.2-2x on 40^3, 56^3, 72^3, 80^3, 80x80x16,
-// 48x48x16): both sides of C at least 40 and not both multiples of 32, and
-// every operand span fits the staging buffer.  Shapes with both sides
+// kernel (1.2-2x on 40^3, 56^3, 72^3, 80^3, 80x80x16, 48x48x16): both sides
+// of C at least 40 and not both multiples of 32, and every operand span
+// fits the staging buffer.  Shapes with both sides
 // multiples of 32, or one side of 16 or less, stay on the strided kernel,
 // whose one-block-per-work-group grid suits them better.
 static bool strided_to_staged(int ta, int tb, int64_t m, int64_t n, int64_t k, int64_t lda,

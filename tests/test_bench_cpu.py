@@ -1,5 +1,5 @@
 """bench.py's command-line contract that needs no GPU: more than one GPU is
-refused with a message (this build measures one GPU), and the counter
+refused with a message (the benchmark measures one GPU), and the counter
 profile it reports traffic from is well formed."""
 import json
 import os
