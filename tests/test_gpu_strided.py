@@ -103,3 +103,41 @@ def test_strided_quick_return_and_errors(ctx):
         iaat.iaat_gemm_strided_batched(ctx, 0, 0, m, n, 4, 1.0, dC.data_ptr(), m, 0, dC.data_ptr(),
                                        3, 0, 0.0, dC.data_ptr(), m, m * n, batch, s)
     assert e.value.code == -12
+
+
+@pytest.mark.parametrize("lay", ["NN", "TN", "NT", "TT"])
+def test_staged_route_padded_leading_dimensions_and_beta_zero(ctx, lay):
+    """A shape the library runs on the staged batched kernel (56 x 72 x 40),
+    with leading dimensions larger than the matrices and stride 0 for B (one
+    B shared by every problem): bitwise equal to per-call iaat_gemm; with
+    beta = 0 and NaN in C, C is not read."""
+    m, n, k, batch = 56, 72, 40, 257
+    ta, tb, ra, ca, rb, cb = stored(lay, m, n, k)
+    lda, ldb, ldc = ra + 3, rb + 5, m + 2
+    sa, sb, sc = lda * ca, 0, ldc * n
+    rng = np.random.Generator(np.random.PCG64(inputs.SEED_BASE + 97))
+    A = rng.uniform(-1, 1, sa * batch).astype(np.float32)
+    B = rng.uniform(-1, 1, ldb * cb).astype(np.float32)
+    s = torch.cuda.current_stream(DEV).cuda_stream
+    dA, dB = torch.from_numpy(A).to(DEV), torch.from_numpy(B).to(DEV)
+    for be in (0.5, 0.0):
+        print("[staged-route] lay=%s beta=%g" % (lay, be), flush=True)
+        C = rng.uniform(-1, 1, sc * batch).astype(np.float32)
+        if be == 0.0:
+            C[:] = np.nan
+        dC1, dC2 = torch.from_numpy(C).to(DEV), torch.from_numpy(C).to(DEV)
+        iaat.iaat_gemm_strided_batched(ctx, int(ta), int(tb), m, n, k, 0.75, dA.data_ptr(), lda, sa,
+                                       dB.data_ptr(), ldb, sb, be, dC1.data_ptr(), ldc, sc, batch, s)
+        L = iaat.lib()
+        for z in range(batch):
+            L.iaat_gemm(ctx, int(ta), int(tb), m, n, k, 0.75, dA.data_ptr() + 4 * z * sa, lda,
+                        dB.data_ptr(), ldb, be, dC2.data_ptr() + 4 * z * sc, ldc, s)
+        torch.cuda.synchronize(DEV)
+        c1, c2 = dC1.cpu().numpy(), dC2.cpu().numpy()
+        assert np.array_equal(c1.view(np.uint32), c2.view(np.uint32))
+        got = c1.reshape(batch, n, ldc)[:, :, :m]
+        if be == 0.0:
+            assert np.isfinite(got).all()
+        # rows m..ldc-1 of every column untouched
+        assert np.array_equal(c1.reshape(batch, n, ldc)[:, :, m:].view(np.uint32),
+                              C.reshape(batch, n, ldc)[:, :, m:].view(np.uint32))
