@@ -285,7 +285,7 @@ int iaat_gemm_strided_batched(iaat_ctx_t ctx, int ta, int tb, int64_t m, int64_t
     return fail(IAAT_ERR_UNSUPPORTED, "iaat_gemm_strided_batched: %lld x %lld is too large",
                 (long long)m, (long long)n);
   dev::Prob P{A, B, C, (int)m, (int)n, (int)k, (int)lda, (int)ldb, (int)ldc, alpha, beta};
-  if (strided_to_staged(ta, tb, m, n, k, lda, ldb, ldc)) {
+  if (batch <= 0x7fffffffLL && strided_to_staged(ta, tb, m, n, k, lda, ldb, ldc)) {
     // the staged batched kernel, on descriptors written on the device (the
     // same blocks in the same order: bitwise the same C)
     iaat_problem* d = nullptr;
